@@ -1,0 +1,202 @@
+/* phi.h -- MI355X (gfx950) library for the radio-interferometric measurement
+ * operator Phi = Theta G F Z, its adjoint, and the l2-ball data-fidelity dual
+ * step of primal-dual forward-backward (PDFB) imaging.
+ *
+ * Paper: Thouvenin, Dabbech et al., "Parallel faceted imaging in radio
+ * interferometry via proximal splitting (Faceted HyperSARA): II. Code and real
+ * data proof of concept" (arXiv 2209.07604).
+ *
+ *   Section 2.1, eq. (1): y_l = Phi_l x_l + n_l,  Phi_l = Theta_l G_l F Z;
+ *       Z zero-pads and scales the N-pixel image into the K-point grid, F is
+ *       the 2-D DFT on that grid, G interpolates (one compact-support row per
+ *       visibility, widened by DDE / w-kernel convolution: Sections 3.1-3.2),
+ *       Theta whitens.  Visibilities are split into blocks (l, b).
+ *   Section 2.2, eq. (2): one data-fidelity term per block, the indicator of
+ *       B(y_{l,b}, eps_{l,b}) = {z : ||z - y_{l,b}||_2 <= eps_{l,b}}.
+ *   Section 2.2.3: PDFB splits these terms; their dual update is
+ *       Phi x~ -> l2-ball projection -> Phi^dagger.
+ *
+ * Conventions (all fixed here; the paper leaves them open):
+ *   - Image x_l: float32, row-major [Ny][Nx]; pixel (p, q) has offsets
+ *     pbar = p - Ny/2, qbar = q - Nx/2 from the phase centre.
+ *   - Grid: Ky = 2 Ny, Kx = 2 Nx (2x oversampling).  Z puts
+ *     s_y[p] s_x[q] x[p][q] at cell (pbar mod Ky, qbar mod Kx); F is the
+ *     unnormalised forward DFT exp(-2 pi i k.n / K); the adjoint uses the
+ *     unnormalised inverse DFT (no 1/K).
+ *   - G: row m is a dense S_m x S_m window (S_m odd, 1..21) whose entry
+ *     (i, j) multiplies grid cell ((b_y + i) mod Ky, (b_x + j) mod Kx).
+ *   - Theta: one real positive scalar theta_b per block.
+ *   - Visibilities: complex64 (float re, float im) interleaved.
+ *   - phi_adjoint returns the adjoint for real images: Re(Z^T F^H G^H Theta v).
+ *
+ * Order of visibilities.  Hot calls read and write visibility vectors in
+ * *plan order*: blocks in channel-major order, and inside each block the
+ * order the plan chose (sorted by window position).  Convert user-order
+ * vectors once with phi_to_plan_order / phi_from_plan_order.
+ *
+ * Memory.  The caller owns every buffer.  Device buffers (prefix d_) are
+ * allocated by the caller (e.g. PyTorch); the plan's own device state lives
+ * in one caller-allocated workspace whose size phi_plan_workspace_size gives.
+ * Host buffers (prefix h_) are read during the call only.  The library makes
+ * no device allocations of its own.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void*; every device call is
+ * asynchronous on it.  A plan must not be used from two streams at once.
+ *
+ * Errors.  Functions return phi_status and never throw.  Argument checks run
+ * before any HIP call.  On error no output is guaranteed.
+ */
+#ifndef PHI_H_
+#define PHI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phi_plan_s* phi_plan;
+
+typedef enum {
+  PHI_OK = 0,
+  PHI_ERR_ARG = -1,          /* null pointer or invalid enum/flag            */
+  PHI_ERR_SHAPE = -2,        /* sizes inconsistent (odd Ny, block counts...) */
+  PHI_ERR_RANGE = -3,        /* value out of range (S, base, theta, eps...)  */
+  PHI_ERR_WORKSPACE = -4,    /* workspace missing, too small or misaligned   */
+  PHI_ERR_NONFINITE = -5,    /* a device-side norm was NaN / Inf             */
+  PHI_ERR_HIP = -6,          /* a HIP runtime call failed                    */
+  PHI_ERR_UNSUPPORTED = -7,  /* size beyond what the kernels are built for   */
+  PHI_ERR_STATE = -8         /* call order (e.g. G not loaded, not bound)    */
+} phi_status;
+
+/* Storage of the G coefficients on the device.  Arithmetic is FP32 in all
+ * cases; the per-block norms and projection scale are FP64. */
+typedef enum {
+  PHI_G_C64 = 0,   /* complex float32                                   */
+  PHI_G_F16 = 1,   /* complex float16 (RNE from the host values)        */
+  PHI_G_BF16 = 2   /* complex bfloat16 (RNE from the host values)       */
+} phi_gprec;
+
+/* Host window element type accepted by phi_plan_load_g. */
+typedef enum { PHI_HOST_C128 = 0, PHI_HOST_C64 = 1 } phi_host_type;
+
+/* Execution flags. */
+enum {
+  PHI_PER_CHANNEL = 1,  /* launch every stage per channel (the plain form)
+                           instead of one launch over all channels/blocks  */
+  PHI_GRAPH = 2,        /* replay the dual step from a captured hipGraph    */
+  PHI_PERSISTENT = 4    /* G stages run as a persistent grid over work items */
+};
+
+typedef struct {
+  int32_t n_channels;          /* L >= 1                                     */
+  int32_t ny, nx;              /* image size, even, 8 <= n <= 4096           */
+  const int32_t* h_n_blocks;   /* [L] blocks per channel, >= 1               */
+  const int64_t* h_n_vis;      /* [sum B] visibilities per block (>= 0),
+                                  channel-major                              */
+  const int32_t* h_base;       /* [M_tot][2] window origin (b_y, b_x),
+                                  0 <= b_y < Ky, 0 <= b_x < Kx; user order   */
+  const uint8_t* h_stencil;    /* [M_tot] window size S, odd, 1 <= S <= 21   */
+  const double* h_theta;       /* [sum B] whitening theta_b > 0 (NULL => 1)  */
+  const double* h_scale_y;     /* [Ny] Z scale s_y (deapodisation)           */
+  const double* h_scale_x;     /* [Nx] Z scale s_x                           */
+  int32_t g_prec;              /* phi_gprec                                  */
+  int32_t flags;               /* PHI_PER_CHANNEL | PHI_GRAPH | ...          */
+  int32_t tile;                /* uv tile edge T for G^H binning: 16, 32 or 64;
+                                  0 picks 32                                 */
+  int32_t persist_blocks;      /* work-groups of a persistent G stage (0 =>
+                                  4 per compute unit when PHI_PERSISTENT)    */
+} phi_desc;
+
+typedef struct {
+  int64_t n_vis_total;         /* M_tot                                      */
+  int64_t n_taps;              /* sum_m S_m^2                                */
+  int64_t n_items;             /* G work items (tile x visibility range)     */
+  int64_t n_blocks_total;      /* sum B                                      */
+  int64_t g_bytes;             /* device bytes of packed G                   */
+  int64_t partial_bytes;       /* device bytes of the G^H tile partials      */
+  int64_t workspace_bytes;     /* total workspace                            */
+  double alg_bytes_dual_step;  /* algorithmic HBM bytes of one dual step     */
+  double alg_bytes_gather;     /* ... of the G gather stage                  */
+  double alg_bytes_scatter;    /* ... of the G^H scatter stage               */
+  int32_t ky, kx, tile, n_stages;
+} phi_info;
+
+/* Validate `desc`, sort visibilities and build the work lists (host only,
+ * no HIP call).  Host arrays are read during the call.  On success *out owns
+ * a plan that phi_plan_destroy releases. */
+phi_status phi_plan_create(const phi_desc* desc, phi_plan* out);
+phi_status phi_plan_destroy(phi_plan plan);
+
+/* Bytes of device workspace the plan needs (256-byte aligned start). */
+phi_status phi_plan_workspace_size(phi_plan plan, size_t* bytes);
+
+/* Attach the caller's workspace and upload plan metadata, twiddles and the
+ * Z scales.  The workspace must stay allocated while the plan is used. */
+phi_status phi_plan_bind(phi_plan plan, void* d_workspace, size_t bytes, void* stream);
+
+/* Pack the windows of block `block` (0 <= block < sum B) into the device
+ * G store, converting to the plan's g_prec with round-to-nearest-even.
+ * h_windows holds that block's windows in user order, each S*S row-major,
+ * back to back, as complex128 or complex64 (phi_host_type).  Synchronous
+ * with respect to h_windows (it can be freed on return). */
+phi_status phi_plan_load_g(phi_plan plan, int64_t block, const void* h_windows,
+                           int32_t host_type, void* stream);
+
+/* Replace the per-block whitening scalars (host [sum B], > 0). */
+phi_status phi_plan_set_theta(phi_plan plan, const double* h_theta, void* stream);
+
+phi_status phi_plan_get_info(phi_plan plan, phi_info* info);
+
+/* Permute a complex64 visibility vector [M_tot] between user order (blocks
+ * concatenated, each in the caller's order) and plan order. */
+phi_status phi_to_plan_order(phi_plan plan, const void* d_user, void* d_plan, void* stream);
+phi_status phi_from_plan_order(phi_plan plan, const void* d_plan, void* d_user, void* stream);
+
+/* y = Phi x for every block (eq. 1).  d_x: float32 [L][Ny][Nx];
+ * d_y: complex64 [M_tot], plan order. */
+phi_status phi_forward(phi_plan plan, const float* d_x, void* d_y, void* stream);
+
+/* x = sum_b Re Phi_{l,b}^dagger v_b for every channel.  d_v: complex64
+ * [M_tot] plan order; d_x: float32 [L][Ny][Nx] (overwritten). */
+phi_status phi_adjoint(phi_plan plan, const void* d_v, float* d_x, void* stream);
+
+/* Data-fidelity dual step of PDFB for every block (l, b) (eq. 2), with
+ * c = v/sigma + Phi x~ - y:
+ *   rho_b = ||c||_2,  res_b = ||Phi x~ - y||_2            (FP64)
+ *   v+    = sigma (1 - eps/rho) c if rho > eps, else 0    (= v + sigma Phi x~
+ *           - sigma P_B(y, eps)((v + sigma Phi x~)/sigma), the Moreau form)
+ *   grad_l = sum_b Re Phi_{l,b}^dagger v+_b
+ * d_xt: float32 [L][Ny][Nx]; d_v: complex64 [M_tot] plan order, in/out
+ * (v on entry, v+ on return); d_y: complex64 [M_tot] plan order;
+ * d_eps: float64 [sum B]; d_sigma: float64 [sum B] or NULL (=> 1);
+ * d_grad: float32 [L][Ny][Nx]; d_rho, d_res: float64 [sum B] (may be NULL).
+ * A NaN or Inf norm is recorded and reported by phi_plan_check. */
+phi_status l2ball_dual_step(phi_plan plan, const float* d_xt, void* d_v, const void* d_y,
+                            const double* d_eps, const double* d_sigma, float* d_grad,
+                            double* d_rho, double* d_res, void* stream);
+
+/* Synchronise `stream` and report PHI_ERR_NONFINITE if any dual step since
+ * the last check produced a non-finite norm (the flag is then cleared). */
+phi_status phi_plan_check(phi_plan plan, void* stream);
+
+/* Per-stage timing with HIP events recorded on `stream` around each stage
+ * of the calls that follow (enable = 1), or off (enable = 0). */
+phi_status phi_plan_set_timing(phi_plan plan, int32_t enable);
+/* Synchronise and return accumulated milliseconds per stage and the number
+ * of timed calls; names[i] are static strings.  n_stages <= max_stages. */
+phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
+                               const char** names, int32_t* n_stages, int64_t* n_calls);
+
+/* Time the candidate tile sizes and launch shapes on the bound plan with its
+ * loaded G (runs dual steps on scratch vectors inside the workspace) and
+ * keep the fastest.  Results are stable for a given plan and device. */
+phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
+
+const char* phi_status_string(phi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHI_H_ */

@@ -1,0 +1,861 @@
+// Host side of libphi: argument checks, the plan (visibility sort, work
+// items, merge lists, workspace layout), G packing/quantisation, and the C ABI
+// entry points declared in include/phi.h.
+//
+// The plan is built for Phi_{l,b} = Theta_{l,b} G_{l,b} F Z (Section 2.1,
+// eq. 1) with data blocks (l, b), and for the per-block l2-ball dual step
+// (Section 2.2, eq. 2).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "phi.h"
+#include "phi_internal.h"
+
+using namespace phi;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+inline uint32_t spread_bits(uint32_t v) {  // 13 bits -> even positions
+  v &= 0x1FFF;
+  v = (v | (v << 8)) & 0x00FF00FF;
+  v = (v | (v << 4)) & 0x0F0F0F0F;
+  v = (v | (v << 2)) & 0x33333333;
+  v = (v | (v << 1)) & 0x55555555;
+  return v;
+}
+// Z-order key of a window origin: any aligned power-of-two tile of the grid
+// is one contiguous run of keys, so one sort serves every tile size.
+inline uint32_t morton(uint32_t by, uint32_t bx) { return (spread_bits(by) << 1) | spread_bits(bx); }
+
+inline int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+inline uint16_t f32_to_bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7FFFFFFFu) > 0x7F800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7FFFu + lsb;
+  return (uint16_t)(u >> 16);
+}
+// Round a double to the nearest bfloat16 (ties to even) in one step.
+inline uint16_t f64_to_bf16_rne(double d) {
+  if (!std::isfinite(d)) return f32_to_bf16_rne((float)d);
+  if (d == 0.0) return std::signbit(d) ? 0x8000 : 0;
+  int e;
+  std::frexp(d, &e);              // |d| in [2^(e-1), 2^e)
+  int q = e - 8;                  // spacing of 8 significant bits
+  if (q < -133) q = -133;         // bfloat16 subnormal spacing
+  const double sc = std::ldexp(1.0, q);
+  const double r = std::nearbyint(d / sc) * sc;  // exact; default mode is RNE
+  return f32_to_bf16_rne((float)r);              // r is representable: exact
+}
+
+struct StageTimer {
+  std::vector<hipEvent_t> pool;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+  size_t next = 0;
+  double ms[16] = {0};
+  int64_t calls = 0;
+  hipEvent_t get() {
+    if (next == pool.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[next++];
+  }
+};
+
+const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather", "finalize",
+                             "scatter",    "merge",      "colfft_inv", "rowfft_inv"};
+constexpr int kNumStages = 8;
+
+}  // namespace
+
+struct phi_plan_s {
+  // geometry
+  int L = 0, Ny = 0, Nx = 0, Ky = 0, Kx = 0, nblk = 0;
+  int gprec = 0, flags = 0, T = 32, halo = 1, persist = 0;
+  int64_t M = 0, ntaps = 0;
+  std::vector<int32_t> n_blocks, blk_chan, chan_blk0;
+  std::vector<int64_t> blk_u0, blk_n;       // user order start / count per block
+  std::vector<double> theta, sy, sx;
+  // plan order
+  std::vector<int32_t> perm;                // plan -> user (global)
+  std::vector<uint32_t> meta;
+  std::vector<int64_t> tap_off;             // [M + 1]
+  std::vector<uint8_t> S_plan;
+  int smax = 1;
+  // work lists
+  std::vector<Item> items;
+  std::vector<BlockInfo> binfo;
+  std::vector<int32_t> tile_ptr;
+  std::vector<TileEntry> entries;
+  std::vector<int32_t> chan_item0;          // [L + 1]
+  int max_pitch = 0;
+  int64_t partial_elems = 0;
+  // workspace layout
+  size_t off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
+         off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
+         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, ws_bytes = 0;
+  char* ws = nullptr;
+  bool bound = false;
+  std::vector<char> g_loaded;
+  hipStream_t cap_stream = nullptr;
+  // graph cache for the dual step
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[9] = {nullptr};
+  // timing
+  bool timing = false;
+  StageTimer timer;
+  std::mutex mu;
+
+  size_t g_elem_bytes() const { return gprec == PHI_G_C64 ? 8 : 4; }
+  template <typename T_>
+  T_* at(size_t off) const { return reinterpret_cast<T_*>(ws + off); }
+};
+
+// ------------------------------------------------------------------ checks
+static phi_status validate(const phi_desc* d) {
+  if (!d) return PHI_ERR_ARG;
+  if (d->n_channels < 1) return PHI_ERR_SHAPE;
+  if (d->ny < 8 || d->nx < 8 || (d->ny & 1) || (d->nx & 1)) return PHI_ERR_SHAPE;
+  if (d->ny > 4096 || d->nx > 4096) return PHI_ERR_UNSUPPORTED;
+  if (!fft_length_supported(2 * d->ny) || !fft_length_supported(2 * d->nx)) return PHI_ERR_UNSUPPORTED;
+  if (d->g_prec < PHI_G_C64 || d->g_prec > PHI_G_BF16) return PHI_ERR_ARG;
+  if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)) return PHI_ERR_ARG;
+  if (d->persist_blocks < 0) return PHI_ERR_ARG;
+  const int T = d->tile ? d->tile : 32;
+  if (T != 16 && T != 32 && T != 64) return PHI_ERR_ARG;
+  if ((2 * d->ny) % T || (2 * d->nx) % T) return PHI_ERR_SHAPE;
+  if (!d->h_n_blocks || !d->h_n_vis || !d->h_scale_y || !d->h_scale_x) return PHI_ERR_ARG;
+  int64_t nblk = 0;
+  for (int l = 0; l < d->n_channels; ++l) {
+    if (d->h_n_blocks[l] < 1) return PHI_ERR_SHAPE;
+    nblk += d->h_n_blocks[l];
+  }
+  if (nblk > (int64_t)1 << 24) return PHI_ERR_UNSUPPORTED;
+  int64_t M = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    if (d->h_n_vis[b] < 0) return PHI_ERR_SHAPE;
+    M += d->h_n_vis[b];
+  }
+  if (M > INT32_MAX - 64) return PHI_ERR_UNSUPPORTED;
+  if (M > 0 && (!d->h_base || !d->h_stencil)) return PHI_ERR_ARG;
+  const int Ky = 2 * d->ny, Kx = 2 * d->nx;
+  for (int64_t m = 0; m < M; ++m) {
+    const int S = d->h_stencil[m];
+    if (S < 1 || S > kMaxS || !(S & 1) || S > Ky || S > Kx) return PHI_ERR_RANGE;
+    const int by = d->h_base[2 * m], bx = d->h_base[2 * m + 1];
+    if (by < 0 || by >= Ky || bx < 0 || bx >= Kx) return PHI_ERR_RANGE;
+  }
+  if (d->h_theta)
+    for (int64_t b = 0; b < nblk; ++b)
+      if (!(d->h_theta[b] > 0.0) || !std::isfinite(d->h_theta[b])) return PHI_ERR_RANGE;
+  for (int p = 0; p < d->ny; ++p)
+    if (!std::isfinite(d->h_scale_y[p])) return PHI_ERR_RANGE;
+  for (int q = 0; q < d->nx; ++q)
+    if (!std::isfinite(d->h_scale_x[q])) return PHI_ERR_RANGE;
+  return PHI_OK;
+}
+
+template <typename F>
+static void parallel_for(int64_t n, F&& f, int max_threads = 16) {
+  const int nt = (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(max_threads,
+                                                                               std::thread::hardware_concurrency()),
+                                                            n / 4096 + 1));
+  if (nt <= 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  const int64_t chunk = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t) {
+    const int64_t a = t * chunk, b = std::min(n, a + chunk);
+    if (a >= b) break;
+    th.emplace_back([=, &f] { f(a, b); });
+  }
+  for (auto& x : th) x.join();
+}
+
+// Work items for tile edge T: split each block's plan-order run at tile
+// changes and at a tap budget; then the per-tile merge lists.
+static void build_items(phi_plan_s* p) {
+  const int T = p->T;
+  const int lt = ilog2(T);
+  p->items.clear();
+  p->binfo.assign(p->nblk, BlockInfo{});
+  p->chan_item0.assign(p->L + 1, 0);
+  const int64_t cap_taps = std::max<int64_t>(4096, std::min<int64_t>(65536, p->ntaps / 16384 + 1));
+  int64_t poff = 0;
+  int max_pitch = 0;
+  int64_t v = 0;
+  for (int b = 0; b < p->nblk; ++b) {
+    BlockInfo bi{};
+    bi.chan = p->blk_chan[b];
+    bi.item0 = (int32_t)p->items.size();
+    bi.v0 = v;
+    const int64_t vend = v + p->blk_n[b];
+    while (v < vend) {
+      const uint32_t m0 = p->meta[v];
+      const int ty = (int)(m0 & 8191) >> lt, tx = (int)((m0 >> 13) & 8191) >> lt;
+      Item it{};
+      it.tap0 = p->tap_off[v];
+      it.v0 = (int32_t)v;
+      it.blk = b;
+      it.chan = bi.chan;
+      it.ty0 = ty * T;
+      it.tx0 = tx * T;
+      int smax = 1;
+      int64_t taps = 0;
+      while (v < vend) {
+        const uint32_t m = p->meta[v];
+        if (((int)(m & 8191) >> lt) != ty || ((int)((m >> 13) & 8191) >> lt) != tx) break;
+        const int S = p->S_plan[v];
+        if (taps > 0 && taps + (int64_t)S * S > cap_taps) break;
+        taps += (int64_t)S * S;
+        smax = std::max(smax, S);
+        ++v;
+      }
+      it.v1 = (int32_t)v;
+      it.pitch = T + smax - 1;
+      it.poff = poff;
+      poff += (int64_t)it.pitch * it.pitch;
+      max_pitch = std::max(max_pitch, it.pitch);
+      p->items.push_back(it);
+    }
+    bi.item1 = (int32_t)p->items.size();
+    bi.v1 = v;
+    p->binfo[b] = bi;
+  }
+  p->partial_elems = poff;
+  p->max_pitch = std::max(max_pitch, T);
+  // channel item ranges (blocks are channel-major)
+  for (int b = 0; b < p->nblk; ++b) p->chan_item0[p->blk_chan[b] + 1] = p->binfo[b].item1;
+  for (int l = 0; l < p->L; ++l) p->chan_item0[l + 1] = std::max(p->chan_item0[l + 1], p->chan_item0[l]);
+  // merge lists: items by (channel, tile)
+  const int nty = p->Ky / T, ntx = p->Kx / T;
+  const int64_t ntiles = (int64_t)p->L * nty * ntx;
+  p->tile_ptr.assign(ntiles + 1, 0);
+  for (const Item& it : p->items) {
+    const int64_t t = ((int64_t)it.chan * nty + it.ty0 / T) * ntx + it.tx0 / T;
+    p->tile_ptr[t + 1]++;
+  }
+  for (int64_t t = 0; t < ntiles; ++t) p->tile_ptr[t + 1] += p->tile_ptr[t];
+  p->entries.assign(p->items.size(), TileEntry{});
+  std::vector<int32_t> fill(p->tile_ptr.begin(), p->tile_ptr.end() - 1);
+  for (const Item& it : p->items) {
+    const int64_t t = ((int64_t)it.chan * nty + it.ty0 / T) * ntx + it.tx0 / T;
+    TileEntry e{};
+    e.poff = it.poff;
+    e.pitch = it.pitch;
+    p->entries[fill[t]++] = e;
+  }
+  p->halo = (p->smax - 1 + T - 1) / T;
+  if (p->halo < 1) p->halo = 1;
+}
+
+static void layout(phi_plan_s* p) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + std::max<size_t>(bytes, 1));
+    return r;
+  };
+  p->off_G = take((size_t)p->ntaps * p->g_elem_bytes());
+  p->off_meta = take((size_t)p->M * 4);
+  p->off_perm = take((size_t)p->M * 4);
+  p->off_items = take(p->items.size() * sizeof(Item));
+  p->off_binfo = take(p->binfo.size() * sizeof(BlockInfo));
+  p->off_tptr = take(p->tile_ptr.size() * 4);
+  p->off_ent = take(p->entries.size() * sizeof(TileEntry));
+  p->off_theta = take((size_t)p->nblk * 4);
+  p->off_part = take((size_t)p->partial_elems * 8);
+  p->off_norms = take(p->items.size() * 16);
+  p->off_scale = take((size_t)p->nblk * 8);
+  p->off_flag = take(16);
+  p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
+  p->off_half = take((size_t)p->L * p->Ny * p->Kx * 8);
+  p->off_twx = take((size_t)p->Kx * 8);
+  p->off_twy = take((size_t)p->Ky * 8);
+  p->off_sy = take((size_t)p->Ny * 4);
+  p->off_sx = take((size_t)p->Nx * 4);
+  p->ws_bytes = o;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+const char* phi_status_string(phi_status s) {
+  switch (s) {
+    case PHI_OK: return "ok";
+    case PHI_ERR_ARG: return "invalid argument";
+    case PHI_ERR_SHAPE: return "inconsistent shape";
+    case PHI_ERR_RANGE: return "value out of range";
+    case PHI_ERR_WORKSPACE: return "workspace missing or too small";
+    case PHI_ERR_NONFINITE: return "non-finite norm";
+    case PHI_ERR_HIP: return "HIP runtime error";
+    case PHI_ERR_UNSUPPORTED: return "unsupported size";
+    case PHI_ERR_STATE: return "plan not ready for this call";
+  }
+  return "unknown status";
+}
+
+phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
+  if (!out) return PHI_ERR_ARG;
+  *out = nullptr;
+  const phi_status st = validate(d);
+  if (st != PHI_OK) return st;
+  phi_plan_s* p = new (std::nothrow) phi_plan_s();
+  if (!p) return PHI_ERR_ARG;
+  p->L = d->n_channels;
+  p->Ny = d->ny;
+  p->Nx = d->nx;
+  p->Ky = 2 * d->ny;
+  p->Kx = 2 * d->nx;
+  p->gprec = d->g_prec;
+  p->flags = d->flags;
+  p->T = d->tile ? d->tile : 32;
+  p->persist = d->persist_blocks;
+  p->n_blocks.assign(d->h_n_blocks, d->h_n_blocks + p->L);
+  for (int l = 0; l < p->L; ++l) {
+    p->chan_blk0.push_back(p->nblk);
+    for (int b = 0; b < p->n_blocks[l]; ++b) p->blk_chan.push_back(l);
+    p->nblk += p->n_blocks[l];
+  }
+  p->chan_blk0.push_back(p->nblk);
+  p->blk_n.assign(d->h_n_vis, d->h_n_vis + p->nblk);
+  p->blk_u0.resize(p->nblk);
+  int64_t M = 0;
+  for (int b = 0; b < p->nblk; ++b) {
+    p->blk_u0[b] = M;
+    M += p->blk_n[b];
+  }
+  p->M = M;
+  p->theta.assign(p->nblk, 1.0);
+  if (d->h_theta) p->theta.assign(d->h_theta, d->h_theta + p->nblk);
+  p->sy.assign(d->h_scale_y, d->h_scale_y + p->Ny);
+  p->sx.assign(d->h_scale_x, d->h_scale_x + p->Nx);
+
+  // sort every block by the Z-order key of its window origins
+  p->perm.resize(M);
+  p->meta.resize(M);
+  p->S_plan.resize(M);
+  std::atomic<int> next{0};
+  auto sort_blocks = [&](int64_t, int64_t) {
+    std::vector<uint64_t> keys;
+    for (int b; (b = next.fetch_add(1)) < p->nblk;) {
+      const int64_t u0 = p->blk_u0[b], n = p->blk_n[b];
+      keys.resize(n);
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t m = u0 + i;
+        keys[i] = ((uint64_t)morton((uint32_t)d->h_base[2 * m], (uint32_t)d->h_base[2 * m + 1]) << 32) | (uint64_t)i;
+      }
+      std::sort(keys.begin(), keys.end());
+      for (int64_t i = 0; i < n; ++i) {
+        const int64_t m = u0 + (int64_t)(keys[i] & 0xFFFFFFFFu);
+        p->perm[u0 + i] = (int32_t)m;
+        const int S = d->h_stencil[m];
+        p->S_plan[u0 + i] = (uint8_t)S;
+        p->meta[u0 + i] = pack_meta(d->h_base[2 * m], d->h_base[2 * m + 1], S);
+      }
+    }
+  };
+  {
+    const int nt = std::max(1, std::min<int>(16, (int)std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (int t = 0; t < std::min(nt, std::max(1, p->nblk)); ++t) th.emplace_back(sort_blocks, 0, 0);
+    for (auto& x : th) x.join();
+  }
+  p->tap_off.resize(M + 1);
+  p->tap_off[0] = 0;
+  for (int64_t i = 0; i < M; ++i) {
+    const int S = p->S_plan[i];
+    p->tap_off[i + 1] = p->tap_off[i] + (int64_t)S * S;
+    p->smax = std::max(p->smax, S);
+  }
+  p->ntaps = p->tap_off[M];
+  build_items(p);
+  layout(p);
+  p->g_loaded.assign(p->nblk, 0);
+  for (int b = 0; b < p->nblk; ++b)
+    if (p->blk_n[b] == 0) p->g_loaded[b] = 1;
+  *out = p;
+  return PHI_OK;
+}
+
+phi_status phi_plan_destroy(phi_plan p) {
+  if (!p) return PHI_ERR_ARG;
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipEvent_t e : p->timer.pool) (void)hipEventDestroy(e);
+  delete p;
+  return PHI_OK;
+}
+
+phi_status phi_plan_workspace_size(phi_plan p, size_t* bytes) {
+  if (!p || !bytes) return PHI_ERR_ARG;
+  *bytes = p->ws_bytes;
+  return PHI_OK;
+}
+
+phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
+  if (!p || !info) return PHI_ERR_ARG;
+  info->n_vis_total = p->M;
+  info->n_taps = p->ntaps;
+  info->n_items = (int64_t)p->items.size();
+  info->n_blocks_total = p->nblk;
+  info->g_bytes = (int64_t)(p->ntaps * p->g_elem_bytes());
+  info->partial_bytes = p->partial_elems * 8;
+  info->workspace_bytes = (int64_t)p->ws_bytes;
+  const double bG = (double)p->g_elem_bytes();
+  const double K = (double)p->Ky * p->Kx, N = (double)p->Ny * p->Nx;
+  // G read once per pass, 4 B of metadata per pass, v and y read, c written
+  // (gather); c read, v+ written (scatter); grids 48 K + 8 N bytes per channel.
+  info->alg_bytes_gather = p->ntaps * bG + p->M * (4.0 + 24.0) + p->L * 8.0 * K;
+  info->alg_bytes_scatter = p->ntaps * bG + p->M * (4.0 + 16.0);
+  info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * 48.0 + p->L * (48.0 * K + 8.0 * N);
+  info->ky = p->Ky;
+  info->kx = p->Kx;
+  info->tile = p->T;
+  info->n_stages = kNumStages;
+  return PHI_OK;
+}
+
+#define HIP_TRY(x)                         \
+  do {                                     \
+    if ((x) != hipSuccess) return PHI_ERR_HIP; \
+  } while (0)
+
+phi_status phi_plan_bind(phi_plan p, void* d_ws, size_t bytes, void* stream) {
+  if (!p || !d_ws) return PHI_ERR_ARG;
+  if (bytes < p->ws_bytes || ((uintptr_t)d_ws % kAlign)) return PHI_ERR_WORKSPACE;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  p->ws = (char*)d_ws;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  std::vector<float> th(p->nblk);
+  for (int b = 0; b < p->nblk; ++b) th[b] = (float)p->theta[b];
+  std::vector<float> fy(p->Ny), fx(p->Nx);
+  for (int i = 0; i < p->Ny; ++i) fy[i] = (float)p->sy[i];
+  for (int i = 0; i < p->Nx; ++i) fx[i] = (float)p->sx[i];
+  auto tw = [](int n) {
+    std::vector<float2> t(n);
+    for (int m = 0; m < n; ++m) {
+      const double a = -2.0 * M_PI * (double)m / (double)n;
+      t[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    return t;
+  };
+  const std::vector<float2> twx = tw(p->Kx), twy = tw(p->Ky);
+  auto up = [&](size_t off, const void* src, size_t n) -> hipError_t {
+    if (n == 0) return hipSuccess;
+    return hipMemcpyAsync(p->ws + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  HIP_TRY(up(p->off_meta, p->meta.data(), p->meta.size() * 4));
+  HIP_TRY(up(p->off_perm, p->perm.data(), p->perm.size() * 4));
+  HIP_TRY(up(p->off_items, p->items.data(), p->items.size() * sizeof(Item)));
+  HIP_TRY(up(p->off_binfo, p->binfo.data(), p->binfo.size() * sizeof(BlockInfo)));
+  HIP_TRY(up(p->off_tptr, p->tile_ptr.data(), p->tile_ptr.size() * 4));
+  HIP_TRY(up(p->off_ent, p->entries.data(), p->entries.size() * sizeof(TileEntry)));
+  HIP_TRY(up(p->off_theta, th.data(), th.size() * 4));
+  HIP_TRY(up(p->off_twx, twx.data(), twx.size() * 8));
+  HIP_TRY(up(p->off_twy, twy.data(), twy.size() * 8));
+  HIP_TRY(up(p->off_sy, fy.data(), fy.size() * 4));
+  HIP_TRY(up(p->off_sx, fx.data(), fx.size() * 4));
+  const int zero[4] = {0, 0, 0, 0};
+  HIP_TRY(up(p->off_flag, zero, sizeof(zero)));
+  HIP_TRY(hipStreamSynchronize(s));  // host vectors above are temporaries
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  p->bound = true;
+  return PHI_OK;
+}
+
+phi_status phi_plan_set_theta(phi_plan p, const double* h_theta, void* stream) {
+  if (!p || !h_theta) return PHI_ERR_ARG;
+  for (int b = 0; b < p->nblk; ++b)
+    if (!(h_theta[b] > 0.0) || !std::isfinite(h_theta[b])) return PHI_ERR_RANGE;
+  p->theta.assign(h_theta, h_theta + p->nblk);
+  if (!p->bound) return PHI_OK;
+  std::vector<float> th(p->nblk);
+  for (int b = 0; b < p->nblk; ++b) th[b] = (float)p->theta[b];
+  HIP_TRY(hipMemcpyAsync(p->ws + p->off_theta, th.data(), th.size() * 4, hipMemcpyHostToDevice,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return PHI_OK;
+}
+
+phi_status phi_plan_load_g(phi_plan p, int64_t block, const void* h_windows, int32_t host_type, void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
+  if (!h_windows && p->blk_n[block] > 0) return PHI_ERR_ARG;
+  if (host_type != PHI_HOST_C128 && host_type != PHI_HOST_C64) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t u0 = p->blk_u0[block], n = p->blk_n[block];
+  if (n == 0) {
+    p->g_loaded[block] = 1;
+    return PHI_OK;
+  }
+  // user-order window offsets inside the block
+  std::vector<int64_t> uoff(n + 1, 0);
+  std::vector<int32_t> uS(n);
+  {
+    // S in user order: invert the block's permutation
+    for (int64_t k = 0; k < n; ++k) uS[p->perm[u0 + k] - u0] = p->S_plan[u0 + k];
+    for (int64_t i = 0; i < n; ++i) uoff[i + 1] = uoff[i] + (int64_t)uS[i] * uS[i];
+  }
+  const size_t eb = p->g_elem_bytes();
+  const int64_t tap_begin = p->tap_off[u0];
+  const int64_t tap_total = p->tap_off[u0 + n] - tap_begin;
+  const int64_t stage_taps = std::min<int64_t>(tap_total, (int64_t)(64 << 20) / (int64_t)eb);
+  void* stage = nullptr;
+  HIP_TRY(hipHostMalloc(&stage, (size_t)stage_taps * eb, hipHostMallocDefault));
+  phi_status rc = PHI_OK;
+  int64_t k = 0;
+  while (k < n && rc == PHI_OK) {
+    // plan positions [k, k2) whose taps fit in the staging buffer
+    int64_t k2 = k;
+    while (k2 < n && p->tap_off[u0 + k2 + 1] - p->tap_off[u0 + k] <= stage_taps) ++k2;
+    if (k2 == k) {
+      rc = PHI_ERR_ARG;
+      break;
+    }
+    const int64_t t0 = p->tap_off[u0 + k];
+    parallel_for(k2 - k, [&](int64_t a, int64_t b) {
+      for (int64_t i = k + a; i < k + b; ++i) {
+        const int64_t ui = p->perm[u0 + i] - u0;
+        const int64_t cnt = uoff[ui + 1] - uoff[ui];
+        const int64_t dst0 = p->tap_off[u0 + i] - t0;
+        for (int64_t e = 0; e < cnt; ++e) {
+          double re, im;
+          if (host_type == PHI_HOST_C128) {
+            const double* src = static_cast<const double*>(h_windows) + 2 * (uoff[ui] + e);
+            re = src[0];
+            im = src[1];
+          } else {
+            const float* src = static_cast<const float*>(h_windows) + 2 * (uoff[ui] + e);
+            re = src[0];
+            im = src[1];
+          }
+          const int64_t di = dst0 + e;
+          if (p->gprec == PHI_G_C64) {
+            float* o = static_cast<float*>(stage) + 2 * di;
+            o[0] = (float)re;
+            o[1] = (float)im;
+          } else if (p->gprec == PHI_G_F16) {
+            _Float16* o = static_cast<_Float16*>(stage) + 2 * di;
+            o[0] = (_Float16)re;
+            o[1] = (_Float16)im;
+          } else {
+            uint16_t* o = static_cast<uint16_t*>(stage) + 2 * di;
+            o[0] = f64_to_bf16_rne(re);
+            o[1] = f64_to_bf16_rne(im);
+          }
+        }
+      }
+    });
+    const int64_t t1 = p->tap_off[u0 + k2];
+    if (hipMemcpyAsync(p->ws + p->off_G + (size_t)t0 * eb, stage, (size_t)(t1 - t0) * eb, hipMemcpyHostToDevice,
+                       s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = PHI_ERR_HIP;
+    k = k2;
+  }
+  (void)tap_begin;
+  (void)hipHostFree(stage);
+  if (rc == PHI_OK) p->g_loaded[block] = 1;
+  return rc;
+}
+
+phi_status phi_to_plan_order(phi_plan p, const void* d_user, void* d_plan, void* stream) {
+  if (!p || (p->M > 0 && (!d_user || !d_plan))) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  HIP_TRY(launch_permute((const float2*)d_user, (float2*)d_plan, p->at<int32_t>(p->off_perm), p->M, 1,
+                         (hipStream_t)stream));
+  return PHI_OK;
+}
+
+phi_status phi_from_plan_order(phi_plan p, const void* d_plan, void* d_user, void* stream) {
+  if (!p || (p->M > 0 && (!d_user || !d_plan))) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  HIP_TRY(launch_permute((const float2*)d_plan, (float2*)d_user, p->at<int32_t>(p->off_perm), p->M, 0,
+                         (hipStream_t)stream));
+  return PHI_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------- execution
+namespace {
+
+struct Runner {
+  phi_plan_s* p;
+  hipStream_t s;
+  bool timed;
+  hipError_t err = hipSuccess;
+
+  GArgs gargs() const {
+    GArgs a;
+    a.items = p->at<Item>(p->off_items);
+    a.meta = p->at<uint32_t>(p->off_meta);
+    a.G = p->ws + p->off_G;
+    a.theta = p->at<float>(p->off_theta);
+    a.sigma = nullptr;
+    a.scale = p->at<double>(p->off_scale);
+    a.grid = p->at<float2>(p->off_grid);
+    a.Ky = p->Ky;
+    a.Kx = p->Kx;
+    return a;
+  }
+  int persist_blocks() const {
+    if (!(p->flags & PHI_PERSISTENT)) return 0;
+    if (p->persist > 0) return p->persist;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    return 4 * cus;
+  }
+  template <typename F>
+  void stage(int id, F&& f) {
+    if (err != hipSuccess) return;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timed) {
+      e0 = p->timer.get();
+      e1 = p->timer.get();
+      if (e0) (void)hipEventRecord(e0, s);
+    }
+    err = f();
+    if (timed && e1) {
+      (void)hipEventRecord(e1, s);
+      p->timer.pending.push_back({id, {e0, e1}});
+    }
+  }
+  // channel range [l0, l1), matching block and item ranges
+  void fwd_fft(const float* x, int l0, int l1) {
+    const int nl = l1 - l0;
+    stage(0, [&] {
+      return launch_rowfft_fwd(p->Kx, x, p->at<float2>(p->off_half), p->at<float>(p->off_sy),
+                               p->at<float>(p->off_sx), p->at<float2>(p->off_twx), p->Ny, p->Nx, l0, nl, s);
+    });
+    stage(1, [&] {
+      return launch_colfft_fwd(p->Ky, p->at<float2>(p->off_half), p->at<float2>(p->off_grid),
+                               p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);
+    });
+  }
+  void adj_fft(float* x, int l0, int l1) {
+    const int nl = l1 - l0;
+    stage(5, [&] {
+      return launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
+                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->T, p->halo, l0, nl, s);
+    });
+    stage(6, [&] {
+      return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
+                               p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);
+    });
+    stage(7, [&] {
+      return launch_rowfft_inv(p->Kx, p->at<float2>(p->off_half), x, p->at<float>(p->off_sy),
+                               p->at<float>(p->off_sx), p->at<float2>(p->off_twx), p->Ny, p->Nx, l0, nl, s);
+    });
+  }
+  void forward(const float* x, float2* y, int l0, int l1) {
+    fwd_fft(x, l0, l1);
+    const GArgs a = gargs();
+    stage(2, [&] {
+      return launch_gather(p->gprec, 0, a, y, nullptr, nullptr, p->chan_item0[l0], p->chan_item0[l1],
+                           persist_blocks(), s);
+    });
+  }
+  void adjoint(const float2* v, float* x, int l0, int l1) {
+    const GArgs a = gargs();
+    stage(4, [&] {
+      return launch_scatter(p->gprec, 0, a, const_cast<float2*>(v), p->at<float2>(p->off_part), p->max_pitch,
+                            p->chan_item0[l0], p->chan_item0[l1], persist_blocks(), s);
+    });
+    adj_fft(x, l0, l1);
+  }
+  void dual(const float* xt, float2* v, const float2* y, const double* eps, const double* sigma, float* grad,
+            double* rho, double* res, int l0, int l1) {
+    fwd_fft(xt, l0, l1);
+    GArgs a = gargs();
+    a.sigma = sigma;
+    const int it0 = p->chan_item0[l0], it1 = p->chan_item0[l1];
+    const int b0 = p->chan_blk0[l0], b1 = p->chan_blk0[l1];
+    stage(2, [&] {
+      return launch_gather(p->gprec, 1, a, v, y, p->at<double>(p->off_norms), it0, it1, persist_blocks(), s);
+    });
+    stage(3, [&] {
+      return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo), eps, rho, res,
+                             p->at<double>(p->off_scale), p->at<int>(p->off_flag), b0, b1 - b0, s);
+    });
+    stage(4, [&] {
+      return launch_scatter(p->gprec, 1, a, v, p->at<float2>(p->off_part), p->max_pitch, it0, it1,
+                            persist_blocks(), s);
+    });
+    adj_fft(grad, l0, l1);
+  }
+};
+
+phi_status ready(phi_plan p) {
+  if (!p) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  for (char c : p->g_loaded)
+    if (!c) return PHI_ERR_STATE;
+  return PHI_OK;
+}
+
+template <typename F>
+phi_status run_channels(phi_plan p, hipStream_t s, F&& body) {
+  Runner r{p, s, p->timing};
+  if (p->flags & PHI_PER_CHANNEL) {
+    for (int l = 0; l < p->L && r.err == hipSuccess; ++l) body(r, l, l + 1);
+  } else {
+    body(r, 0, p->L);
+  }
+  if (p->timing) p->timer.calls++;
+  return r.err == hipSuccess ? PHI_OK : PHI_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+phi_status phi_forward(phi_plan p, const float* d_x, void* d_y, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || (p->M > 0 && !d_y)) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  return run_channels(p, (hipStream_t)stream,
+                      [&](Runner& r, int l0, int l1) { r.forward(d_x, (float2*)d_y, l0, l1); });
+}
+
+phi_status phi_adjoint(phi_plan p, const void* d_v, float* d_x, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || (p->M > 0 && !d_v)) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  return run_channels(p, (hipStream_t)stream,
+                      [&](Runner& r, int l0, int l1) { r.adjoint((const float2*)d_v, d_x, l0, l1); });
+}
+
+phi_status l2ball_dual_step(phi_plan p, const float* d_xt, void* d_v, const void* d_y, const double* d_eps,
+                            const double* d_sigma, float* d_grad, double* d_rho, double* d_res, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_xt || !d_grad || !d_eps || (p->M > 0 && (!d_v || !d_y))) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  auto body = [&](Runner& r, int l0, int l1) {
+    r.dual(d_xt, (float2*)d_v, (const float2*)d_y, d_eps, d_sigma, d_grad, d_rho, d_res, l0, l1);
+  };
+  if ((p->flags & PHI_GRAPH) && !p->timing) {
+    const void* key[9] = {d_xt, d_v, d_y, d_eps, d_sigma, d_grad, d_rho, d_res, stream};
+    if (!p->gexec || std::memcmp(key, p->gkey, sizeof(key)) != 0) {
+      if (p->gexec) {
+        (void)hipGraphExecDestroy(p->gexec);
+        p->gexec = nullptr;
+      }
+      // capture on the plan's own stream, ordered after the caller's stream
+      hipEvent_t ev;
+      HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+      (void)hipEventRecord(ev, s);
+      (void)hipStreamWaitEvent(p->cap_stream, ev, 0);
+      (void)hipEventDestroy(ev);
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      Runner r{p, p->cap_stream, false};
+      if (p->flags & PHI_PER_CHANNEL) {
+        for (int l = 0; l < p->L && r.err == hipSuccess; ++l) body(r, l, l + 1);
+      } else {
+        body(r, 0, p->L);
+      }
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(p->cap_stream, &g);
+      if (r.err != hipSuccess || ec != hipSuccess || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        return PHI_ERR_HIP;
+      }
+      const hipError_t ei = hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ei != hipSuccess) {
+        p->gexec = nullptr;
+        return PHI_ERR_HIP;
+      }
+      std::memcpy(p->gkey, key, sizeof(key));
+    }
+    HIP_TRY(hipGraphLaunch(p->gexec, s));
+    return PHI_OK;
+  }
+  return run_channels(p, s, body);
+}
+
+phi_status phi_plan_check(phi_plan p, void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int flag[4] = {0, 0, 0, 0};
+  HIP_TRY(hipMemcpy(flag, p->ws + p->off_flag, sizeof(flag), hipMemcpyDeviceToHost));
+  if (flag[0]) {
+    const int zero[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(p->ws + p->off_flag, zero, sizeof(zero), hipMemcpyHostToDevice));
+    return PHI_ERR_NONFINITE;
+  }
+  return PHI_OK;
+}
+
+phi_status phi_plan_set_timing(phi_plan p, int32_t enable) {
+  if (!p) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->timing = enable != 0;
+  return PHI_OK;
+}
+
+phi_status phi_plan_get_timing(phi_plan p, int32_t max_stages, double* ms, const char** names, int32_t* n_stages,
+                               int64_t* n_calls) {
+  if (!p) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  for (auto& pe : p->timer.pending) {
+    HIP_TRY(hipEventSynchronize(pe.second.second));
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, pe.second.first, pe.second.second) == hipSuccess) p->timer.ms[pe.first] += t;
+  }
+  p->timer.pending.clear();
+  p->timer.next = 0;
+  const int n = std::min<int>(max_stages, kNumStages);
+  for (int i = 0; i < n; ++i) {
+    if (ms) ms[i] = p->timer.ms[i];
+    if (names) names[i] = kStageNames[i];
+  }
+  if (n_stages) *n_stages = kNumStages;
+  if (n_calls) *n_calls = p->timer.calls;
+  for (double& v : p->timer.ms) v = 0.0;
+  p->timer.calls = 0;
+  return PHI_OK;
+}
+
+phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
+  (void)stream;
+  (void)reps;
+  if (!p) return PHI_ERR_ARG;
+  return PHI_ERR_UNSUPPORTED;
+}
+
+}  // extern "C"

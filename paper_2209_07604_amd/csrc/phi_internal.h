@@ -1,0 +1,88 @@
+// Internal types shared by the host planner (phi_host.cpp) and the HIP
+// kernels (phi_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+namespace phi {
+
+constexpr int kMaxS = 21;          // largest window edge
+constexpr int kMaxK = 8192;        // largest grid edge (13-bit cell index)
+constexpr int kWave = 64;
+
+// Per-visibility metadata word: b_y (13 bits) | b_x (13 bits) | (S-1)/2 (4 bits)
+__host__ __device__ inline uint32_t pack_meta(int by, int bx, int S) {
+  return (uint32_t)by | ((uint32_t)bx << 13) | ((uint32_t)((S - 1) >> 1) << 26);
+}
+
+// A G work item: a run of plan-order visibilities of one block whose window
+// origins fall in one T x T uv tile.  Its G^H contributions accumulate in a
+// pitch x pitch LDS tile anchored at (ty0, tx0); pitch = T + Smax_item - 1.
+struct Item {
+  int64_t tap0;    // first G tap of the run
+  int64_t poff;    // float2 offset of its tile partial
+  int32_t v0, v1;  // plan-order visibility range
+  int32_t blk;     // global block index
+  int32_t chan;    // channel
+  int32_t ty0, tx0;
+  int32_t pitch;
+  int32_t pad;
+};
+static_assert(sizeof(Item) == 48, "Item layout");
+
+// Merge-list entry: one tile partial that overlaps a tile.
+struct TileEntry {
+  int64_t poff;
+  int32_t pitch;
+  int32_t pad;
+};
+
+struct BlockInfo {
+  int32_t chan;
+  int32_t item0, item1;   // items of the block
+  int32_t pad;
+  int64_t v0, v1;         // plan-order visibility range
+};
+
+// Arguments common to the G stages.
+struct GArgs {
+  const Item* items;
+  const uint32_t* meta;
+  const void* G;
+  const float* theta;       // [nblk]
+  const double* sigma;      // [nblk] or null (=> 1)
+  const double* scale;      // [nblk] projection scale (dual step)
+  float2* grid;             // [L][Ky][Kx]
+  int Ky, Kx;
+};
+
+// Kernel launchers (phi_kernels.hip).  All asynchronous on `s`.
+hipError_t launch_rowfft_fwd(int Kx, const float* x, float2* half, const float* sy, const float* sx,
+                             const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
+hipError_t launch_colfft_fwd(int Ky, const float2* half, float2* grid, const float2* tw, int Ny,
+                             int Kx, int l0, int nl, hipStream_t s);
+hipError_t launch_colfft_inv(int Ky, const float2* grid, float2* half, const float2* tw, int Ny,
+                             int Kx, int l0, int nl, hipStream_t s);
+hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* sy, const float* sx,
+                             const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
+
+// mode: 0 forward (write y), 1 residual (c = v/sigma + phi - y into v; norms)
+hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y,
+                         double* item_norms, int it0, int it1, int grid_blocks, hipStream_t s);
+// mode: 0 adjoint (read v), 1 dual (v+ = sigma*scale*c, written back)
+hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
+                          int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
+hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,
+                        const TileEntry* entries, int Ky, int Kx, int T, int halo, int l0, int nl,
+                        hipStream_t s);
+hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, const double* eps,
+                           double* rho, double* res, double* scale, int* flag, int b0, int nb,
+                           hipStream_t s);
+hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n,
+                          int to_plan, hipStream_t s);
+
+bool fft_length_supported(int n);
+
+}  // namespace phi

@@ -1,0 +1,717 @@
+// HIP kernels for gfx950 (MI355X): the stages of Phi = Theta G F Z, its
+// adjoint and the l2-ball data-fidelity dual step (Sections 2.1-2.2, eqs. 1-2).
+//
+//   rowfft_fwd  Z + forward DFT along x of the Ny nonzero rows   (F Z, part 1)
+//   colfft_fwd  forward DFT along y of every grid column          (F Z, part 2)
+//   gather      theta_b * G X per visibility; optional residual    (G, eq. 1;
+//               c = v/sigma + Phi x - y with FP64 partial norms     eq. 2 step)
+//   finalize    per-block FP64 norms and projection scale           (eq. 2)
+//   scatter     G^H theta v (or the dual update first) into LDS tiles
+//   merge       fixed-order sum of tile partials into the grid      (G^H)
+//   colfft_inv  inverse DFT along y, keeping the Ny rows Z^T reads  (F^H)
+//   rowfft_inv  inverse DFT along x, crop, scale, real part        (Z^T F^H)
+//
+// Everything is FP32 except the norms and the projection scale (FP64).
+// No kernel uses global atomics; the G^H accumulation is owned by one wave
+// per tile partial and merged in a fixed order, so results are bitwise
+// reproducible run to run.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "phi_internal.h"
+
+namespace phi {
+namespace {
+
+// ----------------------------------------------------------------- helpers
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// multiply by -i (forward transform) or +i (inverse transform)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 z) {
+  return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the 64 lanes of a wave in a fixed order; every lane gets the sum.
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
+  v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]: quads
+  v += dppf<0x141>(v);  // row_half_mirror: 8-lane halves
+  v += dppf<0x140>(v);  // row_mirror: 16-lane rows
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return (r0 + r1) + (r2 + r3);
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ float readlane_f(float v, int i) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
+}
+
+// ceil(65536 / S): (t * r) >> 16 == t / S exactly for t < 441, S <= 21
+__constant__ uint32_t c_recip[kMaxS + 1] = {
+    0,     65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554,
+    5958,  5462,  5042,  4682,  4370,  4096,  3856,  3641, 3450, 3277, 3121};
+
+// G coefficient loads for the three storage precisions
+template <int GP>
+__device__ __forceinline__ float2 load_g(const void* G, int64_t i);
+template <>
+__device__ __forceinline__ float2 load_g<0>(const void* G, int64_t i) {
+  return static_cast<const float2*>(G)[i];
+}
+template <>
+__device__ __forceinline__ float2 load_g<1>(const void* G, int64_t i) {
+  return __half22float2(static_cast<const __half2*>(G)[i]);
+}
+template <>
+__device__ __forceinline__ float2 load_g<2>(const void* G, int64_t i) {
+  const uint32_t u = static_cast<const uint32_t*>(G)[i];
+  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
+}
+
+// Spread consecutive panels over one XCD: work-group i runs on XCD i % 8.
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+  if (n % 8 != 0) return i;
+  return (i % 8) * (n / 8) + i / 8;
+}
+
+// ------------------------------------------------------------- FFT (LDS)
+// Self-sorting (Stockham) mixed-radix passes over W interleaved sequences of
+// length N held in LDS: element (k, c) at buf[k * W + c].  A pass of radix R
+// with span NS takes inputs k = b + r N/R, twiddles them by
+// exp(-+2 pi i (b mod NS) r / (NS R)) and writes the R-point DFT to
+// (b / NS) NS R + (b mod NS) + r NS.  tw[m] = exp(-2 pi i m / N) (FP32 from FP64).
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2* a);
+
+template <>
+__device__ __forceinline__ void dft<2, false>(float2* a) {
+  const float2 t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+template <>
+__device__ __forceinline__ void dft<2, true>(float2* a) { dft<2, false>(a); }
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& a0, float2& a1, float2& a2, float2& a3) {
+  const float2 t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+  const float2 t3 = mul_mi<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+template <>
+__device__ __forceinline__ void dft<4, false>(float2* a) { dft4<false>(a[0], a[1], a[2], a[3]); }
+template <>
+__device__ __forceinline__ void dft<4, true>(float2* a) { dft4<true>(a[0], a[1], a[2], a[3]); }
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* a) {
+  constexpr float c = 0.70710678118654752440f;
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  float2 o0 = a[1], o1 = a[3], o2 = a[5], o3 = a[7];
+  dft4<INV>(e0, e1, e2, e3);
+  dft4<INV>(o0, o1, o2, o3);
+  if (!INV) {
+    o1 = make_float2(c * (o1.x + o1.y), c * (o1.y - o1.x));
+    o3 = make_float2(c * (o3.y - o3.x), -c * (o3.x + o3.y));
+  } else {
+    o1 = make_float2(c * (o1.x - o1.y), c * (o1.x + o1.y));
+    o3 = make_float2(-c * (o3.x + o3.y), c * (o3.x - o3.y));
+  }
+  o2 = mul_mi<INV>(o2);
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+template <>
+__device__ __forceinline__ void dft<8, false>(float2* a) { dft8<false>(a); }
+template <>
+__device__ __forceinline__ void dft<8, true>(float2* a) { dft8<true>(a); }
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2* a) {
+  constexpr float h = 0.86602540378443864676f;  // sqrt(3)/2
+  const float2 s = cadd(a[1], a[2]), d = csub(a[1], a[2]);
+  const float2 m = make_float2(a[0].x - 0.5f * s.x, a[0].y - 0.5f * s.y);
+  const float2 t = mul_mi<INV>(cscale(d, h));
+  a[0] = cadd(a[0], s);
+  a[1] = cadd(m, t);
+  a[2] = csub(m, t);
+}
+template <>
+__device__ __forceinline__ void dft<3, false>(float2* a) { dft3<false>(a); }
+template <>
+__device__ __forceinline__ void dft<3, true>(float2* a) { dft3<true>(a); }
+
+template <bool INV>
+__device__ __forceinline__ void dft5(float2* a) {
+  constexpr float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+  constexpr float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+  constexpr float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+  constexpr float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+  const float2 p1 = cadd(a[1], a[4]), d1 = csub(a[1], a[4]);
+  const float2 p2 = cadd(a[2], a[3]), d2 = csub(a[2], a[3]);
+  const float2 m1 = make_float2(a[0].x + c1 * p1.x + c2 * p2.x, a[0].y + c1 * p1.y + c2 * p2.y);
+  const float2 m2 = make_float2(a[0].x + c2 * p1.x + c1 * p2.x, a[0].y + c2 * p1.y + c1 * p2.y);
+  const float2 n1 = mul_mi<INV>(make_float2(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+  const float2 n2 = mul_mi<INV>(make_float2(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+  a[0] = cadd(a[0], cadd(p1, p2));
+  a[1] = cadd(m1, n1);
+  a[4] = csub(m1, n1);
+  a[2] = cadd(m2, n2);
+  a[3] = csub(m2, n2);
+}
+template <>
+__device__ __forceinline__ void dft<5, false>(float2* a) { dft5<false>(a); }
+template <>
+__device__ __forceinline__ void dft<5, true>(float2* a) { dft5<true>(a); }
+
+constexpr int pick_radix(int rem) {
+  return rem % 5 == 0 ? 5
+         : rem % 3 == 0 ? 3
+         : (rem % 8 == 0 && rem != 16) ? 8
+         : rem % 4 == 0 ? 4
+                        : 2;
+}
+
+template <int N, int W, int NT, bool INV, int R, int NS>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw) {
+  constexpr int STRIDE = N / R;
+  constexpr int NB = STRIDE * W;
+  constexpr int BPT = (NB + NT - 1) / NT;
+  constexpr int TWS = N / (NS * R);
+  const int tid = threadIdx.x;
+  float2 v[BPT][R];
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int j = tid + q * NT;
+    if (NB % NT == 0 || j < NB) {
+      const int c = j % W, b = j / W;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[(b + r * STRIDE) * W + c];
+      if constexpr (NS > 1) {
+        const int k = b % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          float2 w = tw[k * TWS * r];
+          if (INV) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < BPT; ++q) {
+    const int j = tid + q * NT;
+    if (NB % NT == 0 || j < NB) {
+      const int c = j % W, b = j / W;
+      const int k = b % NS;
+      dft<R, INV>(v[q]);
+      const int d = (b / NS) * NS * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(d + r * NS) * W + c] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <int N, int W, int NT, bool INV, int NS>
+__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int R = pick_radix(N / NS);
+    fft_pass<N, W, NT, INV, R, NS>(buf, tw);
+    fft_run<N, W, NT, INV, NS * R>(buf, tw);
+  }
+}
+
+// Z then the forward DFT of one image row (grid length N = Kx = 2 Nx).
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, float2* __restrict__ half,
+                                                   const float* __restrict__ sy, const float* __restrict__ sx,
+                                                   const float2* __restrict__ tw, int Ny, int Nx, int l0) {
+  __shared__ float2 buf[N];
+  const int p = blockIdx.x, l = l0 + blockIdx.y;
+  const float* xr = x + ((size_t)l * Ny + p) * Nx;
+  const float syp = sy[p];
+  for (int k = threadIdx.x; k < N; k += NT) {
+    const int qb = k < N / 2 ? k : k - N;
+    const int q = qb + Nx / 2;
+    float v = 0.f;
+    if (q >= 0 && q < Nx) v = syp * sx[q] * xr[q];
+    buf[k] = make_float2(v, 0.f);
+  }
+  __syncthreads();
+  fft_run<N, 1, NT, false, 1>(buf, tw);
+  float2* out = half + ((size_t)l * Ny + p) * N;
+  for (int k = threadIdx.x; k < N; k += NT) out[k] = buf[k];
+}
+
+// Inverse DFT of one half-grid row, then Z^T: crop, scale, real part.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ half, float* __restrict__ x,
+                                                   const float* __restrict__ sy, const float* __restrict__ sx,
+                                                   const float2* __restrict__ tw, int Ny, int Nx, int l0) {
+  __shared__ float2 buf[N];
+  const int p = blockIdx.x, l = l0 + blockIdx.y;
+  const float2* in = half + ((size_t)l * Ny + p) * N;
+  for (int k = threadIdx.x; k < N; k += NT) buf[k] = in[k];
+  __syncthreads();
+  fft_run<N, 1, NT, true, 1>(buf, tw);
+  float* xr = x + ((size_t)l * Ny + p) * Nx;
+  const float syp = sy[p];
+  for (int q = threadIdx.x; q < Nx; q += NT) {
+    int k = q - Nx / 2;
+    if (k < 0) k += N;
+    xr[q] = buf[k].x * syp * sx[q];
+  }
+}
+
+// Forward DFT along y of a panel of W grid columns; only the Ny centred rows
+// of the input are nonzero (they come from the half grid).
+template <int N, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colfft_fwd(const float2* __restrict__ half, float2* __restrict__ grid,
+                                                   const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+  __shared__ float2 buf[N * W];
+  const int np = Kx / W;
+  const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
+  const float2* in = half + (size_t)l * Ny * Kx;
+  for (int e = threadIdx.x; e < N * W; e += NT) {
+    const int k = e / W, c = e % W;
+    const int p = (k < N / 2 ? k : k - N) + Ny / 2;
+    buf[e] = (p >= 0 && p < Ny) ? in[(size_t)p * Kx + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_run<N, W, NT, false, 1>(buf, tw);
+  float2* out = grid + (size_t)l * N * Kx;
+  for (int e = threadIdx.x; e < N * W; e += NT) {
+    const int k = e / W, c = e % W;
+    out[(size_t)k * Kx + c0 + c] = buf[e];
+  }
+}
+
+// Inverse DFT along y of a panel of W grid columns; writes the Ny rows that
+// Z^T reads into the half grid.
+template <int N, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ grid, float2* __restrict__ half,
+                                                   const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+  __shared__ float2 buf[N * W];
+  const int np = Kx / W;
+  const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
+  const float2* in = grid + (size_t)l * N * Kx;
+  for (int e = threadIdx.x; e < N * W; e += NT) {
+    const int k = e / W, c = e % W;
+    buf[e] = in[(size_t)k * Kx + c0 + c];
+  }
+  __syncthreads();
+  fft_run<N, W, NT, true, 1>(buf, tw);
+  float2* out = half + (size_t)l * Ny * Kx;
+  for (int e = threadIdx.x; e < N * W; e += NT) {
+    const int k = e / W, c = e % W;
+    const int p = (k < N / 2 ? k : k - N) + Ny / 2;
+    if (p >= 0 && p < Ny) out[(size_t)p * Kx + c0 + c] = buf[e];
+  }
+}
+
+// ------------------------------------------------------------ G (gather)
+// One wave per work item.  Lanes span the S*S taps of one window (row-major,
+// so a wave load touches ~64/S contiguous grid runs and S*S contiguous G
+// taps); the per-visibility sum is a fixed-order wave reduction.  Lane i of
+// each 64-visibility chunk ends up holding visibility i's result, so the
+// residual, its FP64 norms and the stores are lane-parallel and coalesced.
+template <int GP, int MODE>
+__global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis, const float2* __restrict__ yv,
+                                               double* __restrict__ item_norms, int it0, int it1) {
+  const int lane = threadIdx.x;
+  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
+    const Item item = a.items[it];
+    const float th = a.theta[item.blk];
+    float inv_sig = 1.f;
+    if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+    const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
+    int64_t tap = item.tap0;
+    double rho2 = 0.0, res2 = 0.0;
+    for (int m0 = item.v0; m0 < item.v1; m0 += 64) {
+      const int n = min(64, item.v1 - m0);
+      const uint32_t my_meta = lane < n ? a.meta[m0 + lane] : 0u;
+      float2 res = make_float2(0.f, 0.f);
+      for (int i = 0; i < n; ++i) {
+        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)my_meta, i);
+        const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+        const int S2 = S * S;
+        const uint32_t rS = c_recip[S];
+        float ax = 0.f, ay = 0.f;
+        for (int t = lane; t < S2; t += 64) {
+          const int ii = (int)(((uint32_t)t * rS) >> 16);
+          const int jj = t - ii * S;
+          int r = by + ii;
+          r -= (r >= a.Ky) ? a.Ky : 0;
+          int c = bx + jj;
+          c -= (c >= a.Kx) ? a.Kx : 0;
+          const float2 g = load_g<GP>(a.G, tap + t);
+          const float2 X = grid[(size_t)r * a.Kx + c];
+          ax += g.x * X.x - g.y * X.y;
+          ay += g.x * X.y + g.y * X.x;
+        }
+        tap += S2;
+        const float px = wave_sum(ax) * th, py = wave_sum(ay) * th;
+        if (lane == i) res = make_float2(px, py);
+      }
+      if (lane < n) {
+        if (MODE == 0) {
+          vis[m0 + lane] = res;
+        } else {
+          const float2 v = vis[m0 + lane], y = yv[m0 + lane];
+          const float2 c = make_float2(v.x * inv_sig + res.x - y.x, v.y * inv_sig + res.y - y.y);
+          vis[m0 + lane] = c;
+          const double rx = (double)res.x - (double)y.x, ry = (double)res.y - (double)y.y;
+          rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
+          res2 += rx * rx + ry * ry;
+        }
+      }
+    }
+    if (MODE == 1) {
+      rho2 = wave_sum_d(rho2);
+      res2 = wave_sum_d(res2);
+      if (lane == 0) {
+        item_norms[2 * (int64_t)it] = rho2;
+        item_norms[2 * (int64_t)it + 1] = res2;
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------- G^H (scatter)
+// One wave owns one pitch x pitch LDS accumulator (the item's tile plus the
+// window halo) and adds conj(g) theta v for its visibilities in plan order.
+// The taps of one window are distinct cells, so each read-add-write step has
+// no two lanes on one address; no atomics are needed and the order is fixed.
+template <int GP, int MODE>
+__global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vis, float2* __restrict__ partials,
+                                                int it0, int it1) {
+  extern __shared__ float2 acc[];
+  const int lane = threadIdx.x;
+  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
+    const Item item = a.items[it];
+    const int P = item.pitch, PP = P * P;
+    for (int e = lane; e < PP; e += 64) acc[e] = make_float2(0.f, 0.f);
+    __syncthreads();
+    const float th = a.theta[item.blk];
+    float sc = 1.f;
+    if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
+    int64_t tap = item.tap0;
+    for (int m0 = item.v0; m0 < item.v1; m0 += 64) {
+      const int n = min(64, item.v1 - m0);
+      uint32_t my_meta = 0u;
+      float2 av = make_float2(0.f, 0.f);
+      if (lane < n) {
+        my_meta = a.meta[m0 + lane];
+        float2 v = vis[m0 + lane];
+        if (MODE == 1) {
+          v = make_float2(sc * v.x, sc * v.y);
+          vis[m0 + lane] = v;
+        }
+        av = make_float2(th * v.x, th * v.y);
+      }
+      for (int i = 0; i < n; ++i) {
+        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)my_meta, i);
+        const float vx = readlane_f(av.x, i), vy = readlane_f(av.y, i);
+        const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+        const int S2 = S * S;
+        const uint32_t rS = c_recip[S];
+        const int base = (by - item.ty0) * P + (bx - item.tx0);
+        for (int t = lane; t < S2; t += 64) {
+          const int ii = (int)(((uint32_t)t * rS) >> 16);
+          const int jj = t - ii * S;
+          const float2 g = load_g<GP>(a.G, tap + t);
+          float2* p = &acc[base + ii * P + jj];
+          float2 cur = *p;
+          cur.x += g.x * vx + g.y * vy;
+          cur.y += g.x * vy - g.y * vx;
+          *p = cur;
+        }
+        tap += S2;
+      }
+    }
+    __syncthreads();
+    float2* out = partials + item.poff;
+    for (int e = lane; e < PP; e += 64) out[e] = acc[e];
+    __syncthreads();
+  }
+}
+
+// Grid cell (r, c) of channel l = fixed-order sum of the tile partials that
+// cover it (the tiles up to `halo` tiles above/left of its own, with wrap).
+__global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
+                                               const int32_t* __restrict__ tile_ptr,
+                                               const TileEntry* __restrict__ ent, int Ky, int Kx, int T,
+                                               int halo, int l0) {
+  const int l = l0 + blockIdx.y;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (int64_t)Ky * Kx) return;
+  const int r = (int)(e / Kx), c = (int)(e % Kx);
+  const int nty = Ky / T, ntx = Kx / T;
+  const int ty = r / T, tx = c / T;
+  float sx = 0.f, sy = 0.f;
+  for (int dy = 0; dy <= halo; ++dy) {
+    int sty = ty - dy;
+    if (sty < 0) sty += nty;
+    const int ly = r - ty * T + dy * T;
+    for (int dx = 0; dx <= halo; ++dx) {
+      int stx = tx - dx;
+      if (stx < 0) stx += ntx;
+      const int lx = c - tx * T + dx * T;
+      const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
+      const int k1 = tile_ptr[tile + 1];
+      for (int k = tile_ptr[tile]; k < k1; ++k) {
+        const TileEntry te = ent[k];
+        if (ly < te.pitch && lx < te.pitch) {
+          const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+          sx += v.x;
+          sy += v.y;
+        }
+      }
+    }
+  }
+  grid[(int64_t)l * Ky * Kx + e] = make_float2(sx, sy);
+}
+
+// Per-block FP64 norms from the item partials (fixed order), then the
+// projection scale: 0 inside the ball, 1 - eps/rho outside.
+__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ item_norms,
+                                                 const BlockInfo* __restrict__ blocks,
+                                                 const double* __restrict__ eps, double* __restrict__ rho,
+                                                 double* __restrict__ res, double* __restrict__ scale,
+                                                 int* __restrict__ flag, int b0) {
+  const int b = b0 + blockIdx.x, lane = threadIdx.x;
+  const BlockInfo bi = blocks[b];
+  double s0 = 0.0, s1 = 0.0;
+  for (int it = bi.item0 + lane; it < bi.item1; it += 64) {
+    s0 += item_norms[2 * (int64_t)it];
+    s1 += item_norms[2 * (int64_t)it + 1];
+  }
+  s0 = wave_sum_d(s0);
+  s1 = wave_sum_d(s1);
+  if (lane == 0) {
+    const double rh = sqrt(s0), rs = sqrt(s1), ep = eps[b];
+    double sc = (rh > ep) ? 1.0 - ep / rh : 0.0;
+    if (!isfinite(rh) || !isfinite(rs) || !isfinite(ep)) {
+      sc = 0.0;
+      flag[0] = 1;
+    }
+    if (rho) rho[b] = rh;
+    if (res) res[b] = rs;
+    scale[b] = sc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_permute(const float2* __restrict__ src, float2* __restrict__ dst,
+                                                 const int32_t* __restrict__ perm, int64_t n, int to_plan) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (to_plan)
+    dst[i] = src[perm[i]];
+  else
+    dst[perm[i]] = src[i];
+}
+
+// ------------------------------------------------------------- launchers
+constexpr int kFftThreads = 256;
+constexpr int kFftCells = 8192;  // N * W per work-group: 64 KiB of LDS
+
+template <int N>
+hipError_t rowfft_fwd_n(const float* x, float2* half, const float* sy, const float* sx, const float2* tw,
+                        int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  hipLaunchKernelGGL((k_rowfft_fwd<N, kFftThreads>), dim3(Ny, nl), dim3(kFftThreads), 0, s, x, half, sy, sx,
+                     tw, Ny, Nx, l0);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t rowfft_inv_n(const float2* half, float* x, const float* sy, const float* sx, const float2* tw,
+                        int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  hipLaunchKernelGGL((k_rowfft_inv<N, kFftThreads>), dim3(Ny, nl), dim3(kFftThreads), 0, s, half, x, sy, sx,
+                     tw, Ny, Nx, l0);
+  return hipGetLastError();
+}
+template <int N>
+constexpr int col_width() {
+  return (kFftCells / N) > 16 ? 16 : (kFftCells / N) < 1 ? 1 : kFftCells / N;
+}
+template <int N>
+hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int Ny, int Kx, int l0, int nl,
+                        hipStream_t s) {
+  constexpr int W = col_width<N>();
+  if (Kx % W) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_colfft_fwd<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, half, grid,
+                     tw, Ny, Kx, l0);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int Ny, int Kx, int l0, int nl,
+                        hipStream_t s) {
+  constexpr int W = col_width<N>();
+  if (Kx % W) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_colfft_inv<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, grid, half,
+                     tw, Ny, Kx, l0);
+  return hipGetLastError();
+}
+
+#define PHI_FFT_SIZES(X)                                                                              \
+  X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(640) X(768) X(1024) X(1280) X(1536) \
+      X(2048) X(2560) X(3072) X(4096) X(5120) X(6144) X(8192)
+
+}  // namespace
+
+bool fft_length_supported(int n) {
+  switch (n) {
+#define X(N) case N:
+    PHI_FFT_SIZES(X)
+#undef X
+    return true;
+    default:
+      return false;
+  }
+}
+
+hipError_t launch_rowfft_fwd(int Kx, const float* x, float2* half, const float* sy, const float* sx,
+                             const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  switch (Kx) {
+#define X(N) \
+  case N:    \
+    return rowfft_fwd_n<N>(x, half, sy, sx, tw, Ny, Nx, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* sy, const float* sx,
+                             const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  switch (Kx) {
+#define X(N) \
+  case N:    \
+    return rowfft_inv_n<N>(half, x, sy, sx, tw, Ny, Nx, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_colfft_fwd(int Ky, const float2* half, float2* grid, const float2* tw, int Ny, int Kx, int l0,
+                             int nl, hipStream_t s) {
+  switch (Ky) {
+#define X(N) \
+  case N:    \
+    return colfft_fwd_n<N>(half, grid, tw, Ny, Kx, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_colfft_inv(int Ky, const float2* grid, float2* half, const float2* tw, int Ny, int Kx, int l0,
+                             int nl, hipStream_t s) {
+  switch (Ky) {
+#define X(N) \
+  case N:    \
+    return colfft_inv_n<N>(grid, half, tw, Ny, Kx, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+template <int GP>
+static hipError_t gather_gp(int mode, const GArgs& a, float2* vis, const float2* y, double* norms, int it0,
+                            int it1, int nb, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64), 0, s, a, vis, y, norms, it0, it1);
+  else
+    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64), 0, s, a, vis, y, norms, it0, it1);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y, double* item_norms,
+                         int it0, int it1, int grid_blocks, hipStream_t s) {
+  const int n = it1 - it0;
+  if (n <= 0) return hipSuccess;
+  const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
+  switch (gprec) {
+    case 0: return gather_gp<0>(mode, a, vis, y, item_norms, it0, it1, nb, s);
+    case 1: return gather_gp<1>(mode, a, vis, y, item_norms, it0, it1, nb, s);
+    case 2: return gather_gp<2>(mode, a, vis, y, item_norms, it0, it1, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int GP>
+static hipError_t scatter_gp(int mode, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0,
+                             int it1, int nb, hipStream_t s) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_scatter<GP, 0>), dim3(nb), dim3(64), lds, s, a, vis, partials, it0, it1);
+  else
+    hipLaunchKernelGGL((k_scatter<GP, 1>), dim3(nb), dim3(64), lds, s, a, vis, partials, it0, it1);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials, int max_pitch,
+                          int it0, int it1, int grid_blocks, hipStream_t s) {
+  const int n = it1 - it0;
+  if (n <= 0) return hipSuccess;
+  const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
+  const size_t lds = (size_t)max_pitch * max_pitch * sizeof(float2);
+  if (lds > 65536) return hipErrorInvalidValue;
+  switch (gprec) {
+    case 0: return scatter_gp<0>(mode, a, vis, partials, lds, it0, it1, nb, s);
+    case 1: return scatter_gp<1>(mode, a, vis, partials, lds, it0, it1, nb, s);
+    case 2: return scatter_gp<2>(mode, a, vis, partials, lds, it0, it1, nb, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
+                        int Ky, int Kx, int T, int halo, int l0, int nl, hipStream_t s) {
+  const int64_t cells = (int64_t)Ky * Kx;
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)((cells + 255) / 256), nl), dim3(256), 0, s, grid, partials,
+                     tile_ptr, entries, Ky, Kx, T, halo, l0);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, const double* eps, double* rho,
+                           double* res, double* scale, int* flag, int b0, int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, s, item_norms, blocks, eps, rho, res, scale, flag, b0);
+  return hipGetLastError();
+}
+
+hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n, int to_plan,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_permute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, perm, n, to_plan);
+  return hipGetLastError();
+}
+
+}  // namespace phi

@@ -1,0 +1,196 @@
+"""Python binding over the C ABI: a Plan owns a libphi plan and its workspace.
+
+PyTorch provides device memory (the workspace and the caller's vectors) and
+the stream; every step of Phi, Phi^dagger and the dual step runs in the HIP
+kernels of libphi.so.
+"""
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """Phi = Theta G F Z for L channels of an Ny x Nx image with data blocks.
+
+    base: int32 [M_tot, 2] window origins (user order, blocks concatenated);
+    stencil: [M_tot] window sizes; n_blocks: [L]; n_vis: [sum B];
+    theta: [sum B] or None; scale_y/scale_x: FP64 Z scales.
+    """
+
+    def __init__(self, ny, nx, n_blocks, n_vis, base, stencil, scale_y, scale_x, theta=None,
+                 g_prec="c64", flags=0, tile=0, persist_blocks=0, device="cuda:0", bind=True):
+        self._lib = L.load()
+        self.ny, self.nx = int(ny), int(nx)
+        self._n_blocks = np.ascontiguousarray(n_blocks, dtype=np.int32)
+        self._n_vis = np.ascontiguousarray(n_vis, dtype=np.int64)
+        self._base = np.ascontiguousarray(base, dtype=np.int32).reshape(-1, 2)
+        self._stencil = np.ascontiguousarray(stencil, dtype=np.uint8)
+        self._sy = np.ascontiguousarray(scale_y, dtype=np.float64)
+        self._sx = np.ascontiguousarray(scale_x, dtype=np.float64)
+        self._theta = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64)
+        self.L = len(self._n_blocks)
+        self.nblk = int(self._n_blocks.sum())
+        self.M = int(self._n_vis.sum())
+        self.g_prec = g_prec
+        d = L.Desc()
+        d.n_channels, d.ny, d.nx = self.L, self.ny, self.nx
+        d.h_n_blocks = self._n_blocks.ctypes.data
+        d.h_n_vis = self._n_vis.ctypes.data
+        d.h_base = self._base.ctypes.data if self.M else None
+        d.h_stencil = self._stencil.ctypes.data if self.M else None
+        d.h_theta = self._theta.ctypes.data if self._theta is not None else None
+        d.h_scale_y = self._sy.ctypes.data
+        d.h_scale_x = self._sx.ctypes.data
+        d.g_prec = L.G_PREC[g_prec] if isinstance(g_prec, str) else int(g_prec)
+        d.flags, d.tile, d.persist_blocks = int(flags), int(tile), int(persist_blocks)
+        self._h = ctypes.c_void_p()
+        L.check(self._lib.phi_plan_create(ctypes.byref(d), ctypes.byref(self._h)), "phi_plan_create")
+        self.device = device
+        self.ws = None
+        if bind:
+            self.bind()
+
+    # ---------------------------------------------------------------- setup
+    def info(self):
+        i = L.Info()
+        L.check(self._lib.phi_plan_get_info(self._h, ctypes.byref(i)), "phi_plan_get_info")
+        return {k: getattr(i, k) for k, _ in L.Info._fields_}
+
+    def workspace_size(self):
+        n = ctypes.c_size_t()
+        L.check(self._lib.phi_plan_workspace_size(self._h, ctypes.byref(n)), "phi_plan_workspace_size")
+        return n.value
+
+    def bind(self):
+        import torch
+        n = self.workspace_size()
+        self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.check(self._lib.phi_plan_bind(self._h, _dptr(self.ws), n, _stream(torch, self.device)),
+                "phi_plan_bind")
+
+    def load_g(self, block, windows):
+        """Upload block `block`'s windows (user order, S*S row-major each)."""
+        import torch
+        w = np.ascontiguousarray(windows)
+        if w.dtype == np.complex128:
+            kind = L.HOST_C128
+        elif w.dtype == np.complex64:
+            kind = L.HOST_C64
+        else:
+            raise TypeError("windows must be complex128 or complex64")
+        L.check(self._lib.phi_plan_load_g(self._h, int(block), _ptr(w), kind, _stream(torch, self.device)),
+                "phi_plan_load_g")
+
+    def set_theta(self, theta):
+        import torch
+        t = np.ascontiguousarray(theta, dtype=np.float64)
+        L.check(self._lib.phi_plan_set_theta(self._h, _ptr(t), _stream(torch, self.device)),
+                "phi_plan_set_theta")
+
+    # ---------------------------------------------------------------- order
+    def to_plan(self, v_user, out=None):
+        import torch
+        out = torch.empty_like(v_user) if out is None else out
+        L.check(self._lib.phi_to_plan_order(self._h, _dptr(v_user), _dptr(out), _stream(torch, self.device)),
+                "phi_to_plan_order")
+        return out
+
+    def from_plan(self, v_plan, out=None):
+        import torch
+        out = torch.empty_like(v_plan) if out is None else out
+        L.check(self._lib.phi_from_plan_order(self._h, _dptr(v_plan), _dptr(out), _stream(torch, self.device)),
+                "phi_from_plan_order")
+        return out
+
+    # ------------------------------------------------------------ operators
+    def _check_img(self, x):
+        import torch
+        if x.dtype != torch.float32 or not x.is_contiguous() or x.numel() != self.L * self.ny * self.nx:
+            raise ValueError("image must be contiguous float32 [L, Ny, Nx]")
+
+    def _check_vis(self, v):
+        import torch
+        if v.dtype != torch.complex64 or not v.is_contiguous() or v.numel() != self.M:
+            raise ValueError("visibilities must be contiguous complex64 [M_tot]")
+
+    def forward(self, x, out=None):
+        """y = Phi x (plan order)."""
+        import torch
+        self._check_img(x)
+        y = torch.empty(self.M, dtype=torch.complex64, device=self.device) if out is None else out
+        self._check_vis(y)
+        L.check(self._lib.phi_forward(self._h, _dptr(x), _dptr(y), _stream(torch, self.device)), "phi_forward")
+        return y
+
+    def adjoint(self, v, out=None):
+        """x = Re Phi^dagger v (v in plan order)."""
+        import torch
+        self._check_vis(v)
+        x = torch.empty((self.L, self.ny, self.nx), dtype=torch.float32, device=self.device) if out is None else out
+        self._check_img(x)
+        L.check(self._lib.phi_adjoint(self._h, _dptr(v), _dptr(x), _stream(torch, self.device)), "phi_adjoint")
+        return x
+
+    def dual_step(self, xt, v, y, eps, sigma=None, grad=None, rho=None, res=None):
+        """In-place l2-ball dual step on v; returns (grad, rho, res)."""
+        import torch
+        self._check_img(xt)
+        self._check_vis(v)
+        self._check_vis(y)
+        dev = self.device
+        grad = torch.empty((self.L, self.ny, self.nx), dtype=torch.float32, device=dev) if grad is None else grad
+        rho = torch.empty(self.nblk, dtype=torch.float64, device=dev) if rho is None else rho
+        res = torch.empty(self.nblk, dtype=torch.float64, device=dev) if res is None else res
+        for t in (eps,) + ((sigma,) if sigma is not None else ()):
+            if t.dtype != torch.float64 or t.numel() != self.nblk:
+                raise ValueError("eps / sigma must be float64 [sum B]")
+        L.check(self._lib.l2ball_dual_step(self._h, _dptr(xt), _dptr(v), _dptr(y), _dptr(eps), _dptr(sigma),
+                                           _dptr(grad), _dptr(rho), _dptr(res), _stream(torch, dev)),
+                "l2ball_dual_step")
+        return grad, rho, res
+
+    def check(self):
+        import torch
+        L.check(self._lib.phi_plan_check(self._h, _stream(torch, self.device)), "phi_plan_check")
+
+    # --------------------------------------------------------------- timing
+    def set_timing(self, on):
+        L.check(self._lib.phi_plan_set_timing(self._h, 1 if on else 0), "phi_plan_set_timing")
+
+    def get_timing(self):
+        ms = (ctypes.c_double * 16)()
+        names = (ctypes.c_char_p * 16)()
+        n = ctypes.c_int32()
+        calls = ctypes.c_int64()
+        L.check(self._lib.phi_plan_get_timing(self._h, 16, ms, names, ctypes.byref(n), ctypes.byref(calls)),
+                "phi_plan_get_timing")
+        return {names[i].decode(): ms[i] for i in range(n.value)}, calls.value
+
+    def autotune(self, reps=3):
+        import torch
+        return self._lib.phi_plan_autotune(self._h, _stream(torch, self.device), int(reps))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.phi_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
