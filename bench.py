@@ -1,0 +1,269 @@
+"""Throughput of the Phi -> l2-ball -> Phi^dagger data-fidelity step on MI355X.
+
+One step = one l2ball_dual_step over every (channel, block) of the workload:
+Z + 2-D FFT, G gather with the residual, FP64 block norms and projection
+scale, G^H scatter of the new dual variable, merge, inverse FFT and Z^T.
+
+Workload (default): 16 channels x 4 blocks, 1024 x 1024 image (2048 x 2048
+grid), 1.5M visibilities per channel, w-projection stencils 7x7 .. 17x17,
+30 dB input SNR, synthetic (seeded) data shaped like the paper's wideband VLA
+data.  Forms timed on the same data: plain FP32 (complex64 G, every stage
+launched per channel), batched FP32, batched FP16-G (the headline), batched
+BF16-G; batched forms replay a hipGraph.
+
+Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Φ+Φ† visibilities/s and HBM GB/s, batched FP16-G vs plain FP32 at ≤2e-3 err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("paper_2209_07604_amd/csrc/phi_kernels.hip", "paper_2209_07604_amd/csrc/phi_host.cpp"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, launch_alg_bytes):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except ValueError:
+        return None
+    if t.get("source_hash") != kernel_source_hash():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def generate(name, log_every=8):
+    import synth
+    prob = synth.make_problem(name)
+    t0 = time.time()
+    blocks = []
+    for k, (l, b) in enumerate(prob.block_list()):
+        blk = prob.block(l, b)
+        w, _ = blk.windows(np.complex64)
+        blocks.append((blk.base, blk.S, w))
+        if k % log_every == 0:
+            log("[bench] generated block %d/%d (%.0f s)" % (k + 1, len(prob.block_list()), time.time() - t0))
+    return prob, blocks
+
+
+def cpu_baseline(prob, budget_s=30.0):
+    """The FP64 oracle's dual step on channel 0 of the same workload, timed on
+    the host cores (numpy/scipy as they stand)."""
+    import oracle
+    from oracle.dual import block_radii
+    t_setup = time.time()
+    sel = [(0, b) for b in range(prob.n_blocks[0])]
+    rng = np.random.default_rng(5)
+    op = oracle.Operator.from_problem(prob, None, blocks=sel)
+    x = prob.image(0).astype(np.float64)
+    Y = op.forward({0: x})
+    V = [0.1 * (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
+    Y = [y + (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
+    eps = block_radii(prob.n_vis[0])
+    log("[bench] cpu baseline set-up %.1f s" % (time.time() - t_setup))
+    n, t_tot = 0, 0.0
+    while n == 0 or (t_tot < budget_s / 3 and n < 3):
+        t0 = time.perf_counter()
+        oracle.dual_step(op, {0: 0.5 * x}, V, Y, eps)
+        t_tot += time.perf_counter() - t0
+        n += 1
+    m = int(sum(prob.n_vis[0]))
+    return {"value": m * n / t_tot, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+            "sample": "channel 0 (%d blocks, %d visibilities, %dx%d grid) of the same workload, FP64 "
+                      "numpy/scipy dual step, %d run(s), %.2f s each; numpy.fft and scipy.sparse run "
+                      "single-threaded" % (len(sel), m, prob.Ky, prob.Kx, n, t_tot / n)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="C2")
+    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_f16,batched_bf16")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the data-fidelity step shards by channel with no exchange, "
+              "and this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    prob, blocks = generate(args.config)
+    L = prob.L
+    n_vis = [len(s) for (_, s, _) in blocks]
+    base = np.concatenate([b for (b, _, _) in blocks])
+    S = np.concatenate([s for (_, s, _) in blocks])
+    s_y, s_x = prob.deapodisation()
+    M = int(len(S))
+    forms = [f for f in args.forms.split(",") if f]
+    precs = sorted({f.split("_")[1] for f in forms}, key=["c64", "f16", "bf16"].index)
+    plans = {}
+    t0 = time.time()
+    for prec in precs:
+        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
+        for k, (_, _, w) in enumerate(blocks):
+            p.load_g(k, w)
+        plans[prec] = p
+        log("[bench] plan %s ready (%.0f s), info %s" % (prec, time.time() - t0, p.info()))
+    del blocks
+
+    # inputs: x~ = x/2, y = theta Phi0 x + n at 30 dB (theta from the c64 form), v ~ 0.1 CN
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(220907604)
+    x = torch.from_numpy(np.stack([prob.image(l) for l in range(L)])).to(dev)
+    pref = plans[precs[0]]
+    y0 = pref.forward(x)
+    ch_of_blk = np.repeat(np.arange(L), prob.n_blocks)
+    starts = np.concatenate([[0], np.cumsum(n_vis)])
+    pw = np.zeros(L)
+    y0h = y0.abs().square().double()
+    for k in range(len(n_vis)):
+        pw[ch_of_blk[k]] += y0h[starts[k]:starts[k + 1]].sum().item()
+    m_ch = np.array([sum(m) for m in prob.n_vis], dtype=np.float64)
+    theta_ch = 1.0 / np.sqrt(pw / m_ch * 1e-3)
+    theta = theta_ch[ch_of_blk]
+    noise = torch.complex(torch.randn(M, generator=gen, device=dev), torch.randn(M, generator=gen, device=dev))
+    noise = noise * (0.5 ** 0.5)
+    th_vis = torch.from_numpy(np.repeat(theta, n_vis).astype(np.float32)).to(dev)
+    y_plan = {}
+    for prec, p in plans.items():
+        p.set_theta(theta)
+        y_plan[prec] = p.to_plan((th_vis * pref.from_plan(y0) + noise).contiguous())
+    v_init = (0.1 * torch.complex(torch.randn(M, generator=gen, device=dev),
+                                  torch.randn(M, generator=gen, device=dev))).contiguous()
+    xt = (0.5 * x).contiguous()
+    # chi-square radii (eq. 2): eps_l^2 = M_l + 2 sqrt(M_l), eps_lb^2 = eps_l^2 M_lb / M_l
+    eps_h = []
+    for nv in prob.n_vis:
+        ml = float(sum(nv))
+        eps_h += [np.sqrt((ml + 2.0 * np.sqrt(ml)) * m / ml) for m in nv]
+    eps = torch.tensor(eps_h, dtype=torch.float64, device=dev)
+    nblk = len(n_vis)
+    torch.cuda.synchronize()
+
+    results = {}
+    for form in forms:
+        kind, prec = form.split("_")
+        p = plans[prec]
+        v = p.to_plan(v_init)
+        v0 = v.clone()
+        grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
+        rho = torch.empty(nblk, dtype=torch.float64, device=dev)
+        res = torch.empty(nblk, dtype=torch.float64, device=dev)
+        if kind == "batched" and not args.no_autotune:
+            rc = p.autotune(3)
+            log("[bench] autotune %s -> rc %d, tile %d, persist %d" % (
+                prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
+        flags_now = p.info()["persist_blocks"] and PERSISTENT
+        p.set_flags((PER_CHANNEL if kind == "plain" else GRAPH) | flags_now)
+        for _ in range(args.warmup):
+            v.copy_(v0)
+            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
+        v.copy_(v0)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_wall = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_wall
+        ms = e0.elapsed_time(e1) / args.steps
+        p.check()
+        # per-stage HIP-event timing over a second run of the same steps
+        # (stage-by-stage launches of the same kernels on the same stream)
+        p.set_flags((PER_CHANNEL if kind == "plain" else 0) | flags_now)
+        v.copy_(v0)
+        torch.cuda.synchronize()
+        p.set_timing(True)
+        for _ in range(args.steps):
+            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
+        torch.cuda.synchronize()
+        p.set_timing(False)
+        stages, calls = p.get_timing()
+        info = info_t = p.info()
+        results[form] = dict(ms_per_step=ms, tile=info_t["tile"], persist_blocks=info_t["persist_blocks"], wall_ms_per_step=1e3 * wall / args.steps,
+                             vis_per_s=M / (ms * 1e-3),
+                             alg_GBs=info["alg_bytes_dual_step"] / (ms * 1e-3) / 1e9,
+                             stage_ms={k_: v_ / max(calls, 1) for k_, v_ in stages.items()},
+                             info=info, rho0=float(rho[0].item()))
+        log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
+            form, ms, M / (ms * 1e-3), {k_: round(v_ / max(calls, 1), 3) for k_, v_ in stages.items()}))
+
+    head = "batched_f16" if "batched_f16" in results else forms[-1]
+    r = results[head]
+    info = r["info"]
+    gather_ms, scatter_ms = r["stage_ms"]["gather"], r["stage_ms"]["scatter"]
+    dom = "gather" if gather_ms >= scatter_ms else "scatter"
+    alg = info["alg_bytes_gather"] if dom == "gather" else info["alg_bytes_scatter"]
+    dur = (gather_ms if dom == "gather" else scatter_ms) * 1e-3
+    achieved = alg / dur / 1e9
+    line = {
+        "metric": METRIC,
+        "value": r["vis_per_s"],
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d channels x %s blocks, %dx%d image (%dx%d grid), %d visibilities, "
+                               "w-stencils %d..%d, 30 dB" % (args.config, L, sorted(set(prob.n_blocks)),
+                                                              prob.Ny, prob.Nx, prob.Ky, prob.Kx, M,
+                                                              int(S.min()), int(S.max())),
+                   "form": head.replace("_", " ") + " (hipGraph)", "g_storage": head.split("_")[1],
+                   "taps": int(info["n_taps"])},
+        "hbm_alg_GBs": r["alg_GBs"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
+                     "avg_launch_ms": dur * 1e3},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
+    }
+    if "plain_c64" in results:
+        line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
+    if not args.no_cpu_baseline:
+        try:
+            line["cpu_baseline"] = cpu_baseline(prob)
+        except MemoryError:
+            line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

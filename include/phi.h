@@ -121,6 +121,9 @@ typedef struct {
   double alg_bytes_gather;     /* ... of the G gather stage                  */
   double alg_bytes_scatter;    /* ... of the G^H scatter stage               */
   int32_t ky, kx, tile, n_stages;
+  int32_t persist_blocks;      /* persistent G-stage grid in use (0 = one
+                                  work-group per item)                       */
+  int32_t reserved;
 } phi_info;
 
 /* Validate `desc`, sort visibilities and build the work lists (host only,
@@ -148,6 +151,10 @@ phi_status phi_plan_load_g(phi_plan plan, int64_t block, const void* h_windows,
 phi_status phi_plan_set_theta(phi_plan plan, const double* h_theta, void* stream);
 
 phi_status phi_plan_get_info(phi_plan plan, phi_info* info);
+
+/* Change the execution flags (PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)
+ * of a plan; the data it holds is unchanged.  Drops a cached graph. */
+phi_status phi_plan_set_flags(phi_plan plan, int32_t flags);
 
 /* Permute a complex64 visibility vector [M_tot] between user order (blocks
  * concatenated, each in the caller's order) and plan order. */
@@ -181,6 +188,12 @@ phi_status l2ball_dual_step(phi_plan plan, const float* d_xt, void* d_v, const v
  * the last check produced a non-finite norm (the flag is then cleared). */
 phi_status phi_plan_check(phi_plan plan, void* stream);
 
+/* Set the tuning choices by hand (what phi_plan_autotune picks): the tile
+ * edge (one the plan was created with: 16/32/64 where they divide the grid,
+ * or only desc->tile if one was given) and the persistent G-stage grid size
+ * (0 = one work-group per item). */
+phi_status phi_plan_set_tuning(phi_plan plan, int32_t tile, int32_t persist_blocks, void* stream);
+
 /* Per-stage timing with HIP events recorded on `stream` around each stage
  * of the calls that follow (enable = 1), or off (enable = 0). */
 phi_status phi_plan_set_timing(phi_plan plan, int32_t enable);
@@ -189,9 +202,11 @@ phi_status phi_plan_set_timing(phi_plan plan, int32_t enable);
 phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
                                const char** names, int32_t* n_stages, int64_t* n_calls);
 
-/* Time the candidate tile sizes and launch shapes on the bound plan with its
- * loaded G (runs dual steps on scratch vectors inside the workspace) and
- * keep the fastest.  Results are stable for a given plan and device. */
+/* Time the candidate tile edges (16, 32, 64, where they divide the grid) and
+ * G-stage launch shapes (one work-group per item, or a persistent grid of 4
+ * work-groups per compute unit) on the bound plan with its loaded G: `reps`
+ * rounds of gather + scatter + merge on scratch vectors inside the
+ * workspace.  Keeps the fastest; overwrites the grid buffers.  Synchronous. */
 phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
 
 const char* phi_status_string(phi_status s);

@@ -22,7 +22,7 @@ PER_CHANNEL, GRAPH, PERSISTENT = 1, 2, 4
 # every symbol include/phi.h declares
 EXPORTS = [
     "phi_plan_create", "phi_plan_destroy", "phi_plan_workspace_size", "phi_plan_bind",
-    "phi_plan_load_g", "phi_plan_set_theta", "phi_plan_get_info", "phi_to_plan_order",
+    "phi_plan_load_g", "phi_plan_set_theta", "phi_plan_get_info", "phi_plan_set_flags", "phi_plan_set_tuning", "phi_to_plan_order",
     "phi_from_plan_order", "phi_forward", "phi_adjoint", "l2ball_dual_step",
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
     "phi_status_string",
@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
         ("workspace_bytes", ctypes.c_int64), ("alg_bytes_dual_step", ctypes.c_double),
         ("alg_bytes_gather", ctypes.c_double), ("alg_bytes_scatter", ctypes.c_double),
         ("ky", ctypes.c_int32), ("kx", ctypes.c_int32), ("tile", ctypes.c_int32),
-        ("n_stages", ctypes.c_int32),
+        ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -86,6 +87,8 @@ def load():
         "phi_plan_load_g": [P, I64, V, I32, V],
         "phi_plan_set_theta": [P, V, V],
         "phi_plan_get_info": [P, ctypes.POINTER(Info)],
+        "phi_plan_set_flags": [P, I32],
+        "phi_plan_set_tuning": [P, I32, I32, V],
         "phi_to_plan_order": [P, V, V, V],
         "phi_from_plan_order": [P, V, V, V],
         "phi_forward": [P, V, V, V],

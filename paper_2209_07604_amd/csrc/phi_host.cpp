@@ -88,10 +88,21 @@ constexpr int kNumStages = 8;
 
 }  // namespace
 
+// The work lists of one tile edge T (G items, block ranges, merge lists).
+struct WorkList {
+  int T = 32, halo = 1, max_pitch = 0;
+  int64_t partial_elems = 0;
+  std::vector<Item> items;
+  std::vector<BlockInfo> binfo;
+  std::vector<int32_t> tile_ptr;
+  std::vector<TileEntry> entries;
+  std::vector<int32_t> chan_item0;          // [L + 1]
+};
+
 struct phi_plan_s {
   // geometry
   int L = 0, Ny = 0, Nx = 0, Ky = 0, Kx = 0, nblk = 0;
-  int gprec = 0, flags = 0, T = 32, halo = 1, persist = 0;
+  int gprec = 0, flags = 0, persist = 0;
   int64_t M = 0, ntaps = 0;
   std::vector<int32_t> n_blocks, blk_chan, chan_blk0;
   std::vector<int64_t> blk_u0, blk_n;       // user order start / count per block
@@ -102,18 +113,15 @@ struct phi_plan_s {
   std::vector<int64_t> tap_off;             // [M + 1]
   std::vector<uint8_t> S_plan;
   int smax = 1;
-  // work lists
-  std::vector<Item> items;
-  std::vector<BlockInfo> binfo;
-  std::vector<int32_t> tile_ptr;
-  std::vector<TileEntry> entries;
-  std::vector<int32_t> chan_item0;          // [L + 1]
-  int max_pitch = 0;
-  int64_t partial_elems = 0;
+  // work lists: one per candidate tile edge, `cur` is in use on the device
+  std::vector<WorkList> cands;
+  int cur = 0;
+  WorkList& W() { return cands[cur]; }
+  const WorkList& W() const { return cands[cur]; }
   // workspace layout
   size_t off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
-         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, ws_bytes = 0;
+         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool bound = false;
   std::vector<char> g_loaded;
@@ -196,12 +204,12 @@ static void parallel_for(int64_t n, F&& f, int max_threads = 16) {
 
 // Work items for tile edge T: split each block's plan-order run at tile
 // changes and at a tap budget; then the per-tile merge lists.
-static void build_items(phi_plan_s* p) {
-  const int T = p->T;
+static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
+  w.T = T;
   const int lt = ilog2(T);
-  p->items.clear();
-  p->binfo.assign(p->nblk, BlockInfo{});
-  p->chan_item0.assign(p->L + 1, 0);
+  w.items.clear();
+  w.binfo.assign(p->nblk, BlockInfo{});
+  w.chan_item0.assign(p->L + 1, 0);
   const int64_t cap_taps = std::max<int64_t>(4096, std::min<int64_t>(65536, p->ntaps / 16384 + 1));
   int64_t poff = 0;
   int max_pitch = 0;
@@ -209,7 +217,7 @@ static void build_items(phi_plan_s* p) {
   for (int b = 0; b < p->nblk; ++b) {
     BlockInfo bi{};
     bi.chan = p->blk_chan[b];
-    bi.item0 = (int32_t)p->items.size();
+    bi.item0 = (int32_t)w.items.size();
     bi.v0 = v;
     const int64_t vend = v + p->blk_n[b];
     while (v < vend) {
@@ -234,41 +242,42 @@ static void build_items(phi_plan_s* p) {
         ++v;
       }
       it.v1 = (int32_t)v;
+      it.ntap = (int32_t)taps;
       it.pitch = T + smax - 1;
       it.poff = poff;
       poff += (int64_t)it.pitch * it.pitch;
       max_pitch = std::max(max_pitch, it.pitch);
-      p->items.push_back(it);
+      w.items.push_back(it);
     }
-    bi.item1 = (int32_t)p->items.size();
+    bi.item1 = (int32_t)w.items.size();
     bi.v1 = v;
-    p->binfo[b] = bi;
+    w.binfo[b] = bi;
   }
-  p->partial_elems = poff;
-  p->max_pitch = std::max(max_pitch, T);
+  w.partial_elems = poff;
+  w.max_pitch = std::max(max_pitch, T);
   // channel item ranges (blocks are channel-major)
-  for (int b = 0; b < p->nblk; ++b) p->chan_item0[p->blk_chan[b] + 1] = p->binfo[b].item1;
-  for (int l = 0; l < p->L; ++l) p->chan_item0[l + 1] = std::max(p->chan_item0[l + 1], p->chan_item0[l]);
+  for (int b = 0; b < p->nblk; ++b) w.chan_item0[p->blk_chan[b] + 1] = w.binfo[b].item1;
+  for (int l = 0; l < p->L; ++l) w.chan_item0[l + 1] = std::max(w.chan_item0[l + 1], w.chan_item0[l]);
   // merge lists: items by (channel, tile)
   const int nty = p->Ky / T, ntx = p->Kx / T;
   const int64_t ntiles = (int64_t)p->L * nty * ntx;
-  p->tile_ptr.assign(ntiles + 1, 0);
-  for (const Item& it : p->items) {
+  w.tile_ptr.assign(ntiles + 1, 0);
+  for (const Item& it : w.items) {
     const int64_t t = ((int64_t)it.chan * nty + it.ty0 / T) * ntx + it.tx0 / T;
-    p->tile_ptr[t + 1]++;
+    w.tile_ptr[t + 1]++;
   }
-  for (int64_t t = 0; t < ntiles; ++t) p->tile_ptr[t + 1] += p->tile_ptr[t];
-  p->entries.assign(p->items.size(), TileEntry{});
-  std::vector<int32_t> fill(p->tile_ptr.begin(), p->tile_ptr.end() - 1);
-  for (const Item& it : p->items) {
+  for (int64_t t = 0; t < ntiles; ++t) w.tile_ptr[t + 1] += w.tile_ptr[t];
+  w.entries.assign(w.items.size(), TileEntry{});
+  std::vector<int32_t> fill(w.tile_ptr.begin(), w.tile_ptr.end() - 1);
+  for (const Item& it : w.items) {
     const int64_t t = ((int64_t)it.chan * nty + it.ty0 / T) * ntx + it.tx0 / T;
     TileEntry e{};
     e.poff = it.poff;
     e.pitch = it.pitch;
-    p->entries[fill[t]++] = e;
+    w.entries[fill[t]++] = e;
   }
-  p->halo = (p->smax - 1 + T - 1) / T;
-  if (p->halo < 1) p->halo = 1;
+  w.halo = (p->smax - 1 + T - 1) / T;
+  if (w.halo < 1) w.halo = 1;
 }
 
 static void layout(phi_plan_s* p) {
@@ -281,13 +290,20 @@ static void layout(phi_plan_s* p) {
   p->off_G = take((size_t)p->ntaps * p->g_elem_bytes());
   p->off_meta = take((size_t)p->M * 4);
   p->off_perm = take((size_t)p->M * 4);
-  p->off_items = take(p->items.size() * sizeof(Item));
-  p->off_binfo = take(p->binfo.size() * sizeof(BlockInfo));
-  p->off_tptr = take(p->tile_ptr.size() * 4);
-  p->off_ent = take(p->entries.size() * sizeof(TileEntry));
+  size_t n_items = 0, n_tptr = 0, n_part = 0;
+  for (const WorkList& w : p->cands) {
+    n_items = std::max(n_items, w.items.size());
+    n_tptr = std::max(n_tptr, w.tile_ptr.size());
+    n_part = std::max(n_part, (size_t)w.partial_elems);
+  }
+  p->off_items = take(n_items * sizeof(Item));
+  p->off_binfo = take((size_t)p->nblk * sizeof(BlockInfo));
+  p->off_tptr = take(n_tptr * 4);
+  p->off_ent = take(n_items * sizeof(TileEntry));
   p->off_theta = take((size_t)p->nblk * 4);
-  p->off_part = take((size_t)p->partial_elems * 8);
-  p->off_norms = take(p->items.size() * 16);
+  p->off_part = take(n_part * 8);
+  p->off_norms = take(n_items * 16);
+  p->off_vscr = take((size_t)p->M * 8);   // scratch visibilities for the autotuner
   p->off_scale = take((size_t)p->nblk * 8);
   p->off_flag = take(16);
   p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
@@ -297,6 +313,20 @@ static void layout(phi_plan_s* p) {
   p->off_sy = take((size_t)p->Ny * 4);
   p->off_sx = take((size_t)p->Nx * 4);
   p->ws_bytes = o;
+}
+
+static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
+  const WorkList& w = p->W();
+  hipError_t e = hipSuccess;
+  auto up = [&](size_t off, const void* src, size_t n) {
+    if (e == hipSuccess && n) e = hipMemcpyAsync(p->ws + off, src, n, hipMemcpyHostToDevice, s);
+  };
+  up(p->off_items, w.items.data(), w.items.size() * sizeof(Item));
+  up(p->off_binfo, w.binfo.data(), w.binfo.size() * sizeof(BlockInfo));
+  up(p->off_tptr, w.tile_ptr.data(), w.tile_ptr.size() * 4);
+  up(p->off_ent, w.entries.data(), w.entries.size() * sizeof(TileEntry));
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
 }
 
 // ------------------------------------------------------------------ ABI
@@ -331,7 +361,6 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
   p->Kx = 2 * d->nx;
   p->gprec = d->g_prec;
   p->flags = d->flags;
-  p->T = d->tile ? d->tile : 32;
   p->persist = d->persist_blocks;
   p->n_blocks.assign(d->h_n_blocks, d->h_n_blocks + p->L);
   for (int l = 0; l < p->L; ++l) {
@@ -391,7 +420,13 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
     p->smax = std::max(p->smax, S);
   }
   p->ntaps = p->tap_off[M];
-  build_items(p);
+  for (int T : {16, 32, 64}) {
+    if (d->tile && d->tile != T) continue;
+    if (p->Ky % T || p->Kx % T) continue;
+    p->cands.emplace_back();
+    build_worklist(p, T, p->cands.back());
+    if (T == (d->tile ? d->tile : 32)) p->cur = (int)p->cands.size() - 1;
+  }
   layout(p);
   p->g_loaded.assign(p->nblk, 0);
   for (int b = 0; b < p->nblk; ++b)
@@ -419,10 +454,10 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   if (!p || !info) return PHI_ERR_ARG;
   info->n_vis_total = p->M;
   info->n_taps = p->ntaps;
-  info->n_items = (int64_t)p->items.size();
+  info->n_items = (int64_t)p->W().items.size();
   info->n_blocks_total = p->nblk;
   info->g_bytes = (int64_t)(p->ntaps * p->g_elem_bytes());
-  info->partial_bytes = p->partial_elems * 8;
+  info->partial_bytes = p->W().partial_elems * 8;
   info->workspace_bytes = (int64_t)p->ws_bytes;
   const double bG = (double)p->g_elem_bytes();
   const double K = (double)p->Ky * p->Kx, N = (double)p->Ny * p->Nx;
@@ -433,8 +468,9 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * 48.0 + p->L * (48.0 * K + 8.0 * N);
   info->ky = p->Ky;
   info->kx = p->Kx;
-  info->tile = p->T;
+  info->tile = p->W().T;
   info->n_stages = kNumStages;
+  info->persist_blocks = (p->flags & PHI_PERSISTENT) ? p->persist : 0;
   return PHI_OK;
 }
 
@@ -473,10 +509,7 @@ phi_status phi_plan_bind(phi_plan p, void* d_ws, size_t bytes, void* stream) {
   };
   HIP_TRY(up(p->off_meta, p->meta.data(), p->meta.size() * 4));
   HIP_TRY(up(p->off_perm, p->perm.data(), p->perm.size() * 4));
-  HIP_TRY(up(p->off_items, p->items.data(), p->items.size() * sizeof(Item)));
-  HIP_TRY(up(p->off_binfo, p->binfo.data(), p->binfo.size() * sizeof(BlockInfo)));
-  HIP_TRY(up(p->off_tptr, p->tile_ptr.data(), p->tile_ptr.size() * 4));
-  HIP_TRY(up(p->off_ent, p->entries.data(), p->entries.size() * sizeof(TileEntry)));
+  HIP_TRY(upload_worklist(p, s));
   HIP_TRY(up(p->off_theta, th.data(), th.size() * 4));
   HIP_TRY(up(p->off_twx, twx.data(), twx.size() * 8));
   HIP_TRY(up(p->off_twy, twy.data(), twy.size() * 8));
@@ -626,6 +659,7 @@ struct Runner {
     a.grid = p->at<float2>(p->off_grid);
     a.Ky = p->Ky;
     a.Kx = p->Kx;
+    a.T = p->W().T;
     return a;
   }
   int persist_blocks() const {
@@ -666,7 +700,7 @@ struct Runner {
     const int nl = l1 - l0;
     stage(5, [&] {
       return launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->T, p->halo, l0, nl, s);
+                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, l0, nl, s);
     });
     stage(6, [&] {
       return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
@@ -681,15 +715,16 @@ struct Runner {
     fwd_fft(x, l0, l1);
     const GArgs a = gargs();
     stage(2, [&] {
-      return launch_gather(p->gprec, 0, a, y, nullptr, nullptr, p->chan_item0[l0], p->chan_item0[l1],
+      return launch_gather(p->gprec, 0, a, y, nullptr, nullptr, p->W().max_pitch, p->W().chan_item0[l0],
+                           p->W().chan_item0[l1],
                            persist_blocks(), s);
     });
   }
   void adjoint(const float2* v, float* x, int l0, int l1) {
     const GArgs a = gargs();
     stage(4, [&] {
-      return launch_scatter(p->gprec, 0, a, const_cast<float2*>(v), p->at<float2>(p->off_part), p->max_pitch,
-                            p->chan_item0[l0], p->chan_item0[l1], persist_blocks(), s);
+      return launch_scatter(p->gprec, 0, a, const_cast<float2*>(v), p->at<float2>(p->off_part), p->W().max_pitch,
+                            p->W().chan_item0[l0], p->W().chan_item0[l1], persist_blocks(), s);
     });
     adj_fft(x, l0, l1);
   }
@@ -698,17 +733,18 @@ struct Runner {
     fwd_fft(xt, l0, l1);
     GArgs a = gargs();
     a.sigma = sigma;
-    const int it0 = p->chan_item0[l0], it1 = p->chan_item0[l1];
+    const int it0 = p->W().chan_item0[l0], it1 = p->W().chan_item0[l1];
     const int b0 = p->chan_blk0[l0], b1 = p->chan_blk0[l1];
     stage(2, [&] {
-      return launch_gather(p->gprec, 1, a, v, y, p->at<double>(p->off_norms), it0, it1, persist_blocks(), s);
+      return launch_gather(p->gprec, 1, a, v, y, p->at<double>(p->off_norms), p->W().max_pitch, it0, it1,
+                           persist_blocks(), s);
     });
     stage(3, [&] {
       return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo), eps, rho, res,
                              p->at<double>(p->off_scale), p->at<int>(p->off_flag), b0, b1 - b0, s);
     });
     stage(4, [&] {
-      return launch_scatter(p->gprec, 1, a, v, p->at<float2>(p->off_part), p->max_pitch, it0, it1,
+      return launch_scatter(p->gprec, 1, a, v, p->at<float2>(p->off_part), p->W().max_pitch, it0, it1,
                             persist_blocks(), s);
     });
     adj_fft(grad, l0, l1);
@@ -821,6 +857,39 @@ phi_status phi_plan_check(phi_plan p, void* stream) {
   return PHI_OK;
 }
 
+phi_status phi_plan_set_flags(phi_plan p, int32_t flags) {
+  if (!p) return PHI_ERR_ARG;
+  if (flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  p->flags = flags;
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  return PHI_OK;
+}
+
+phi_status phi_plan_set_tuning(phi_plan p, int32_t tile, int32_t persist_blocks, void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (persist_blocks < 0) return PHI_ERR_ARG;
+  int c = -1;
+  for (int i = 0; i < (int)p->cands.size(); ++i)
+    if (p->cands[i].T == tile) c = i;
+  if (c < 0) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  p->persist = persist_blocks;
+  p->flags = persist_blocks ? (p->flags | PHI_PERSISTENT) : (p->flags & ~PHI_PERSISTENT);
+  if (c != p->cur) {
+    p->cur = c;
+    if (p->bound && upload_worklist(p, (hipStream_t)stream) != hipSuccess) return PHI_ERR_HIP;
+  }
+  return PHI_OK;
+}
+
 phi_status phi_plan_set_timing(phi_plan p, int32_t enable) {
   if (!p) return PHI_ERR_ARG;
   std::lock_guard<std::mutex> lk(p->mu);
@@ -852,10 +921,81 @@ phi_status phi_plan_get_timing(phi_plan p, int32_t max_stages, double* ms, const
 }
 
 phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
-  (void)stream;
-  (void)reps;
-  if (!p) return PHI_ERR_ARG;
-  return PHI_ERR_UNSUPPORTED;
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  if (reps < 1) reps = 3;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (p->gexec) {
+    (void)hipGraphExecDestroy(p->gexec);
+    p->gexec = nullptr;
+  }
+  // finite grid values for the timed gathers (contents are otherwise unused)
+  HIP_TRY(hipMemsetAsync(p->ws + p->off_grid, 0, (size_t)p->L * p->Ky * p->Kx * 8, s));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int saved_flags = p->flags, saved_persist = p->persist;
+  float2* vs = p->at<float2>(p->off_vscr);
+  // time `reps` rounds of the selected G stages with the current settings
+  auto time_stages = [&](bool g, bool sc, double& ms_out) -> bool {
+    Runner r{p, s, false};
+    auto once = [&] {
+      const GArgs a = r.gargs();
+      const int n = (int)p->W().items.size();
+      if (g && r.err == hipSuccess)
+        r.err = launch_gather(p->gprec, 0, a, vs, nullptr, nullptr, p->W().max_pitch, 0, n, r.persist_blocks(), s);
+      if (sc && r.err == hipSuccess)
+        r.err = launch_scatter(p->gprec, 0, a, vs, p->at<float2>(p->off_part), p->W().max_pitch, 0,
+                               n, r.persist_blocks(), s);
+      if (sc && r.err == hipSuccess)
+        r.err = launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
+                             p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, 0, p->L, s);
+    };
+    once();
+    (void)hipEventRecord(e0, s);
+    for (int k = 0; k < reps && r.err == hipSuccess; ++k) once();
+    (void)hipEventRecord(e1, s);
+    float ms = 0.f;
+    if (r.err != hipSuccess || hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return false;
+    ms_out = ms;
+    return true;
+  };
+  double best = 1e30;
+  int best_c = p->cur, best_p = 0;
+  phi_status rc = PHI_OK;
+  // 1) tile edge x launch shape, both stages
+  for (int c = 0; c < (int)p->cands.size() && rc == PHI_OK; ++c) {
+    p->cur = c;
+    if (upload_worklist(p, s) != hipSuccess) {
+      rc = PHI_ERR_HIP;
+      break;
+    }
+    for (int pb : {0, 4 * cus}) {
+      p->persist = pb;
+      p->flags = pb ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT);
+      double ms = 0;
+      if (!time_stages(true, true, ms)) {
+        rc = PHI_ERR_HIP;
+        break;
+      }
+      if (ms < best) {
+        best = ms;
+        best_c = c;
+        best_p = pb;
+      }
+    }
+  }
+  p->cur = best_c;
+  p->persist = best_p ? best_p : saved_persist;
+  p->flags = best_p ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT);
+  if (rc == PHI_OK && upload_worklist(p, s) != hipSuccess) rc = PHI_ERR_HIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
 }
 
 }  // extern "C"

@@ -28,7 +28,7 @@ struct Item {
   int32_t chan;    // channel
   int32_t ty0, tx0;
   int32_t pitch;
-  int32_t pad;
+  int32_t ntap;    // taps of the run (sum of S^2)
 };
 static_assert(sizeof(Item) == 48, "Item layout");
 
@@ -56,6 +56,7 @@ struct GArgs {
   const double* scale;      // [nblk] projection scale (dual step)
   float2* grid;             // [L][Ky][Kx]
   int Ky, Kx;
+  int T;                    // tile edge of the items (pitch = T + Smax - 1)
 };
 
 // Kernel launchers (phi_kernels.hip).  All asynchronous on `s`.
@@ -70,7 +71,7 @@ hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* 
 
 // mode: 0 forward (write y), 1 residual (c = v/sigma + phi - y into v; norms)
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y,
-                         double* item_norms, int it0, int it1, int grid_blocks, hipStream_t s);
+                         double* item_norms, int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
 // mode: 0 adjoint (read v), 1 dual (v+ = sigma*scale*c, written back)
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
                           int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);

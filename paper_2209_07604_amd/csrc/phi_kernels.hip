@@ -70,23 +70,6 @@ __constant__ uint32_t c_recip[kMaxS + 1] = {
     0,     65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554,
     5958,  5462,  5042,  4682,  4370,  4096,  3856,  3641, 3450, 3277, 3121};
 
-// G coefficient loads for the three storage precisions
-template <int GP>
-__device__ __forceinline__ float2 load_g(const void* G, int64_t i);
-template <>
-__device__ __forceinline__ float2 load_g<0>(const void* G, int64_t i) {
-  return static_cast<const float2*>(G)[i];
-}
-template <>
-__device__ __forceinline__ float2 load_g<1>(const void* G, int64_t i) {
-  return __half22float2(static_cast<const __half2*>(G)[i]);
-}
-template <>
-__device__ __forceinline__ float2 load_g<2>(const void* G, int64_t i) {
-  const uint32_t u = static_cast<const uint32_t*>(G)[i];
-  return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xFFFF0000u));
-}
-
 // Spread consecutive panels over one XCD: work-group i runs on XCD i % 8.
 __device__ __forceinline__ int xcd_remap(int i, int n) {
   if (n % 8 != 0) return i;
@@ -336,61 +319,193 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
 }
 
 // ------------------------------------------------------------ G (gather)
-// One wave per work item.  Lanes span the S*S taps of one window (row-major,
-// so a wave load touches ~64/S contiguous grid runs and S*S contiguous G
-// taps); the per-visibility sum is a fixed-order wave reduction.  Lane i of
-// each 64-visibility chunk ends up holding visibility i's result, so the
-// residual, its FP64 norms and the stores are lane-parallel and coalesced.
+// Raw G storage per precision: complex float, or two 16-bit halves in a word.
+template <int GP>
+struct GRaw {
+  using T = uint32_t;
+};
+template <>
+struct GRaw<0> {
+  using T = float2;
+};
+template <int GP>
+__device__ __forceinline__ float2 unpack_g(typename GRaw<GP>::T r);
+template <>
+__device__ __forceinline__ float2 unpack_g<0>(float2 r) {
+  return r;
+}
+template <>
+__device__ __forceinline__ float2 unpack_g<1>(uint32_t r) {
+  __half2 h;
+  __builtin_memcpy(&h, &r, 4);
+  return __half22float2(h);
+}
+template <>
+__device__ __forceinline__ float2 unpack_g<2>(uint32_t r) {
+  return make_float2(__uint_as_float(r << 16), __uint_as_float(r & 0xFFFF0000u));
+}
+template <int GP>
+__device__ __forceinline__ typename GRaw<GP>::T zero_g() {
+  if constexpr (GP == 0)
+    return make_float2(0.f, 0.f);
+  else
+    return 0u;
+}
+
+__device__ __forceinline__ uint32_t meta_at(uint32_t mcur, uint32_t mnxt, int off) {
+  return (uint32_t)(off < 64 ? __builtin_amdgcn_readlane((int)mcur, off)
+                             : __builtin_amdgcn_readlane((int)mnxt, off - 64));
+}
+
+// One wave per work item (a run of plan-order visibilities of one block whose
+// window origins lie in one T x T uv tile).  Lanes span the S*S taps of one
+// window (row-major); the per-visibility sum is a fixed-order wave reduction.
+//
+// Latency hiding: the G taps of the next D windows are loaded into registers
+// while the current window is reduced.  Each fetch issues exactly NK loads
+// (NK = 64-tap steps of the item's largest window; lanes past a smaller
+// window re-read a valid tap), and the steady-state loop has no guarded
+// fetch, so the wait before a window is used always leaves the later D - 1
+// fetches in flight.  Per-chunk vectors (metadata, v, y) are loaded one
+// 64-visibility chunk ahead of their use.  NK is a template parameter picked
+// per item at run time (1..7 for S <= 21), D = about 12 / NK.
+//
+// Gather: the item's grid region (its tile plus the window halo, wrapped
+// periodically) is first copied into LDS, so each window reads its S*S cells
+// from LDS and only G streams through the vector memory path.  Lane i of
+// each chunk keeps visibility i's result: the residual, its FP64 norms and
+// the stores are lane-parallel and coalesced.
+template <int NK>
+struct Depth {
+  static constexpr int value = NK == 1 ? 12 : NK == 2 ? 6 : NK <= 4 ? 4 : 3;
+};
+
+template <int GP, int MODE, int NK, int D>
+__device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, float2* __restrict__ vis,
+                                            const float2* __restrict__ yv, double& rho2, double& res2,
+                                            const float2* __restrict__ tile) {
+  using R = typename GRaw<GP>::T;
+  const R* __restrict__ G = static_cast<const R*>(a.G);
+  const int lane = threadIdx.x;
+  const int v0 = item.v0, v1 = item.v1, vlast = v1 - 1, P = item.pitch;
+  const float th = a.theta[item.blk];
+  float inv_sig = 1.f;
+  if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+  int cb = v0;
+  uint32_t mcur = a.meta[min(cb + lane, vlast)];
+  uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
+  float2 vc = make_float2(0.f, 0.f), yc = vc;
+  if (MODE == 1) {
+    vc = vis[min(cb + lane, vlast)];
+    yc = yv[min(cb + lane, vlast)];
+  }
+  R gb[D][NK];
+  uint32_t ms[D];
+  int64_t tapf = item.tap0;
+  int jf = v0;
+  auto fetch = [&](R(&g)[NK], uint32_t& m) {
+    const bool live = jf < v1;
+    const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
+    m = mt;
+    const int S = 2 * (int)(mt >> 26) + 1;
+    const int S2 = S * S;
+    const int64_t tb = live ? tapf : item.tap0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) g[k] = G[tb + min(k * 64 + lane, S2 - 1)];
+    tapf += live ? S2 : 0;
+    ++jf;
+  };
+  float2 res = make_float2(0.f, 0.f);
+  auto flush = [&]() {
+    if (cb + lane < v1) {
+      if (MODE == 0) {
+        vis[cb + lane] = res;
+      } else {
+        const float2 c = make_float2(vc.x * inv_sig + res.x - yc.x, vc.y * inv_sig + res.y - yc.y);
+        vis[cb + lane] = c;
+        const double rx = (double)res.x - (double)yc.x, ry = (double)res.y - (double)yc.y;
+        rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
+        res2 += rx * rx + ry * ry;
+      }
+    }
+  };
+  auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
+    if (i == cb + 64) {
+      flush();
+      cb += 64;
+      mcur = mnxt;
+      mnxt = a.meta[min(cb + 64 + lane, vlast)];
+      if (MODE == 1) {
+        vc = vis[min(cb + lane, vlast)];
+        yc = yv[min(cb + lane, vlast)];
+      }
+      res = make_float2(0.f, 0.f);
+    }
+    const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+    const int S2 = S * S;
+    const uint32_t rS = c_recip[S];
+    const int base = (by - item.ty0) * P + (bx - item.tx0);
+    float ax = 0.f, ay = 0.f;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = k * 64 + lane;
+      if (t < S2) {
+        const int ii = (int)(((uint32_t)t * rS) >> 16);
+        const int jj = t - ii * S;
+        const float2 gg = unpack_g<GP>(g[k]);
+        const float2 X = tile[base + ii * P + jj];
+        ax += gg.x * X.x - gg.y * X.y;
+        ay += gg.x * X.y + gg.y * X.x;
+      }
+    }
+    const float px = wave_sum(ax) * th, py = wave_sum(ay) * th;
+    if (lane == i - cb) res = make_float2(px, py);
+  };
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(gb[d], ms[d]);
+  int i = v0;
+  for (; i + D <= v1; i += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      step(gb[d], ms[d], i + d);
+      fetch(gb[d], ms[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (i + d < v1) step(gb[d], ms[d], i + d);
+  if (cb < v1) flush();
+}
+
 template <int GP, int MODE>
 __global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis, const float2* __restrict__ yv,
                                                double* __restrict__ item_norms, int it0, int it1) {
+  extern __shared__ float2 tile[];
   const int lane = threadIdx.x;
   for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
     const Item item = a.items[it];
-    const float th = a.theta[item.blk];
-    float inv_sig = 1.f;
-    if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+    const int P = item.pitch;
+    // copy the item's grid region (rows ty0.., columns tx0.., wrapped)
     const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
-    int64_t tap = item.tap0;
+    for (int e = lane; e < P * P; e += 64) {
+      const int r = e / P, c = e - (e / P) * P;
+      int gr = item.ty0 + r, gc = item.tx0 + c;
+      gr -= (gr >= a.Ky) ? a.Ky : 0;
+      gc -= (gc >= a.Kx) ? a.Kx : 0;
+      tile[e] = grid[(size_t)gr * a.Kx + gc];
+    }
+    __syncthreads();
+    const int smax = P - a.T + 1;
+    const int nk = (smax * smax + 63) / 64;
     double rho2 = 0.0, res2 = 0.0;
-    for (int m0 = item.v0; m0 < item.v1; m0 += 64) {
-      const int n = min(64, item.v1 - m0);
-      const uint32_t my_meta = lane < n ? a.meta[m0 + lane] : 0u;
-      float2 res = make_float2(0.f, 0.f);
-      for (int i = 0; i < n; ++i) {
-        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)my_meta, i);
-        const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
-        const int S2 = S * S;
-        const uint32_t rS = c_recip[S];
-        float ax = 0.f, ay = 0.f;
-        for (int t = lane; t < S2; t += 64) {
-          const int ii = (int)(((uint32_t)t * rS) >> 16);
-          const int jj = t - ii * S;
-          int r = by + ii;
-          r -= (r >= a.Ky) ? a.Ky : 0;
-          int c = bx + jj;
-          c -= (c >= a.Kx) ? a.Kx : 0;
-          const float2 g = load_g<GP>(a.G, tap + t);
-          const float2 X = grid[(size_t)r * a.Kx + c];
-          ax += g.x * X.x - g.y * X.y;
-          ay += g.x * X.y + g.y * X.x;
-        }
-        tap += S2;
-        const float px = wave_sum(ax) * th, py = wave_sum(ay) * th;
-        if (lane == i) res = make_float2(px, py);
-      }
-      if (lane < n) {
-        if (MODE == 0) {
-          vis[m0 + lane] = res;
-        } else {
-          const float2 v = vis[m0 + lane], y = yv[m0 + lane];
-          const float2 c = make_float2(v.x * inv_sig + res.x - y.x, v.y * inv_sig + res.y - y.y);
-          vis[m0 + lane] = c;
-          const double rx = (double)res.x - (double)y.x, ry = (double)res.y - (double)y.y;
-          rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
-          res2 += rx * rx + ry * ry;
-        }
-      }
+    switch (nk) {
+      case 1: gather_item<GP, MODE, 1, Depth<1>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      case 2: gather_item<GP, MODE, 2, Depth<2>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      case 3: gather_item<GP, MODE, 3, Depth<3>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      case 4: gather_item<GP, MODE, 4, Depth<4>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      case 5: gather_item<GP, MODE, 5, Depth<5>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      case 6: gather_item<GP, MODE, 6, Depth<6>::value>(a, item, vis, yv, rho2, res2, tile); break;
+      default: gather_item<GP, MODE, 7, Depth<7>::value>(a, item, vis, yv, rho2, res2, tile); break;
     }
     if (MODE == 1) {
       rho2 = wave_sum_d(rho2);
@@ -400,6 +515,7 @@ __global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis
         item_norms[2 * (int64_t)it + 1] = res2;
       }
     }
+    __syncthreads();
   }
 }
 
@@ -408,6 +524,89 @@ __global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis
 // window halo) and adds conj(g) theta v for its visibilities in plan order.
 // The taps of one window are distinct cells, so each read-add-write step has
 // no two lanes on one address; no atomics are needed and the order is fixed.
+// The G taps are prefetched exactly as in the gather.
+template <int GP, int MODE, int NK, int D>
+__device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, float2* __restrict__ vis,
+                                             float2* __restrict__ acc) {
+  using R = typename GRaw<GP>::T;
+  const R* __restrict__ G = static_cast<const R*>(a.G);
+  const int lane = threadIdx.x;
+  const int v0 = item.v0, v1 = item.v1, vlast = v1 - 1, P = item.pitch;
+  const float th = a.theta[item.blk];
+  float sc = 1.f;
+  if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
+  // theta * v for a chunk (dual form: v+ = sigma * scale * c, written back)
+  auto take_av = [&](float2 v, int c0) -> float2 {
+    if (MODE == 1) {
+      v = make_float2(sc * v.x, sc * v.y);
+      if (c0 + lane < v1) vis[c0 + lane] = v;
+    }
+    return make_float2(th * v.x, th * v.y);
+  };
+  int cb = v0;
+  uint32_t mcur = a.meta[min(cb + lane, vlast)];
+  uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
+  float2 avc = take_av(vis[min(cb + lane, vlast)], cb);
+  float2 vraw = vis[min(cb + 64 + lane, vlast)];
+  R gb[D][NK];
+  uint32_t ms[D];
+  int64_t tapf = item.tap0;
+  int jf = v0;
+  auto fetch = [&](R(&g)[NK], uint32_t& m) {
+    const bool live = jf < v1;
+    const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
+    m = mt;
+    const int S = 2 * (int)(mt >> 26) + 1;
+    const int S2 = S * S;
+    const int64_t tb = live ? tapf : item.tap0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) g[k] = G[tb + min(k * 64 + lane, S2 - 1)];
+    tapf += live ? S2 : 0;
+    ++jf;
+  };
+  auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
+    if (i == cb + 64) {
+      cb += 64;
+      mcur = mnxt;
+      mnxt = a.meta[min(cb + 64 + lane, vlast)];
+      avc = take_av(vraw, cb);
+      vraw = vis[min(cb + 64 + lane, vlast)];
+    }
+    const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+    const int S2 = S * S;
+    const uint32_t rS = c_recip[S];
+    const float vx = readlane_f(avc.x, i - cb), vy = readlane_f(avc.y, i - cb);
+    const int base = (by - item.ty0) * P + (bx - item.tx0);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = k * 64 + lane;
+      if (t < S2) {
+        const int ii = (int)(((uint32_t)t * rS) >> 16);
+        const int jj = t - ii * S;
+        const float2 gg = unpack_g<GP>(g[k]);
+        float2* p = &acc[base + ii * P + jj];
+        float2 cur = *p;
+        cur.x += gg.x * vx + gg.y * vy;
+        cur.y += gg.x * vy - gg.y * vx;
+        *p = cur;
+      }
+    }
+  };
+#pragma unroll
+  for (int d = 0; d < D; ++d) fetch(gb[d], ms[d]);
+  int i = v0;
+  for (; i + D <= v1; i += D) {
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      step(gb[d], ms[d], i + d);
+      fetch(gb[d], ms[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < D - 1; ++d)
+    if (i + d < v1) step(gb[d], ms[d], i + d);
+}
+
 template <int GP, int MODE>
 __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vis, float2* __restrict__ partials,
                                                 int it0, int it1) {
@@ -418,42 +617,16 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
     const int P = item.pitch, PP = P * P;
     for (int e = lane; e < PP; e += 64) acc[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    const float th = a.theta[item.blk];
-    float sc = 1.f;
-    if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
-    int64_t tap = item.tap0;
-    for (int m0 = item.v0; m0 < item.v1; m0 += 64) {
-      const int n = min(64, item.v1 - m0);
-      uint32_t my_meta = 0u;
-      float2 av = make_float2(0.f, 0.f);
-      if (lane < n) {
-        my_meta = a.meta[m0 + lane];
-        float2 v = vis[m0 + lane];
-        if (MODE == 1) {
-          v = make_float2(sc * v.x, sc * v.y);
-          vis[m0 + lane] = v;
-        }
-        av = make_float2(th * v.x, th * v.y);
-      }
-      for (int i = 0; i < n; ++i) {
-        const uint32_t mt = (uint32_t)__builtin_amdgcn_readlane((int)my_meta, i);
-        const float vx = readlane_f(av.x, i), vy = readlane_f(av.y, i);
-        const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
-        const int S2 = S * S;
-        const uint32_t rS = c_recip[S];
-        const int base = (by - item.ty0) * P + (bx - item.tx0);
-        for (int t = lane; t < S2; t += 64) {
-          const int ii = (int)(((uint32_t)t * rS) >> 16);
-          const int jj = t - ii * S;
-          const float2 g = load_g<GP>(a.G, tap + t);
-          float2* p = &acc[base + ii * P + jj];
-          float2 cur = *p;
-          cur.x += g.x * vx + g.y * vy;
-          cur.y += g.x * vy - g.y * vx;
-          *p = cur;
-        }
-        tap += S2;
-      }
+    const int smax = P - a.T + 1;
+    const int nk = (smax * smax + 63) / 64;
+    switch (nk) {
+      case 1: scatter_item<GP, MODE, 1, Depth<1>::value>(a, item, vis, acc); break;
+      case 2: scatter_item<GP, MODE, 2, Depth<2>::value>(a, item, vis, acc); break;
+      case 3: scatter_item<GP, MODE, 3, Depth<3>::value>(a, item, vis, acc); break;
+      case 4: scatter_item<GP, MODE, 4, Depth<4>::value>(a, item, vis, acc); break;
+      case 5: scatter_item<GP, MODE, 5, Depth<5>::value>(a, item, vis, acc); break;
+      case 6: scatter_item<GP, MODE, 6, Depth<6>::value>(a, item, vis, acc); break;
+      default: scatter_item<GP, MODE, 7, Depth<7>::value>(a, item, vis, acc); break;
     }
     __syncthreads();
     float2* out = partials + item.poff;
@@ -462,40 +635,84 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
   }
 }
 
-// Grid cell (r, c) of channel l = fixed-order sum of the tile partials that
-// cover it (the tiles up to `halo` tiles above/left of its own, with wrap).
+// One work-group per (channel, tile): cell (r, c) of the tile is the
+// fixed-order sum of the tile partials covering it (its own tile's items and
+// those of the tiles up to `halo` tiles above/left, with wrap).  The partial
+// list is staged in LDS once per tile; reads of a partial row are coalesced.
+constexpr int kMergeList = 256;
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
                                                const TileEntry* __restrict__ ent, int Ky, int Kx, int T,
                                                int halo, int l0) {
+  __shared__ int64_t s_off[kMergeList];
+  __shared__ int32_t s_pitch[kMergeList];
+  __shared__ int32_t s_oy[kMergeList], s_ox[kMergeList];
+  __shared__ int s_beg[16], s_pre[17];
   const int l = l0 + blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= (int64_t)Ky * Kx) return;
-  const int r = (int)(e / Kx), c = (int)(e % Kx);
   const int nty = Ky / T, ntx = Kx / T;
-  const int ty = r / T, tx = c / T;
-  float sx = 0.f, sy = 0.f;
-  for (int dy = 0; dy <= halo; ++dy) {
-    int sty = ty - dy;
-    if (sty < 0) sty += nty;
-    const int ly = r - ty * T + dy * T;
-    for (int dx = 0; dx <= halo; ++dx) {
-      int stx = tx - dx;
-      if (stx < 0) stx += ntx;
-      const int lx = c - tx * T + dx * T;
-      const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
-      const int k1 = tile_ptr[tile + 1];
-      for (int k = tile_ptr[tile]; k < k1; ++k) {
-        const TileEntry te = ent[k];
-        if (ly < te.pitch && lx < te.pitch) {
-          const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  const int hw = halo + 1, nsrc = hw * hw;   // halo <= 3: at most 16 source tiles
+  if ((int)threadIdx.x < nsrc) {
+    const int dy = threadIdx.x / hw, dx = threadIdx.x % hw;
+    int sty = ty - dy, stx = tx - dx;
+    while (sty < 0) sty += nty;
+    while (stx < 0) stx += ntx;
+    const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
+    s_beg[threadIdx.x] = tile_ptr[tile];
+    s_pre[threadIdx.x + 1] = tile_ptr[tile + 1] - tile_ptr[tile];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    s_pre[0] = 0;
+    for (int j = 0; j < nsrc; ++j) s_pre[j + 1] += s_pre[j];
+  }
+  __syncthreads();
+  const int n = s_pre[nsrc];
+  for (int e = threadIdx.x; e < n && e < kMergeList; e += 256) {
+    int j = 0;
+    while (e >= s_pre[j + 1]) ++j;
+    const TileEntry te = ent[s_beg[j] + (e - s_pre[j])];
+    s_off[e] = te.poff;
+    s_pitch[e] = te.pitch;
+    s_oy[e] = (j / hw) * T;
+    s_ox[e] = (j % hw) * T;
+  }
+  __syncthreads();
+  float2* out = grid + (int64_t)l * Ky * Kx;
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int r = e / T, c = e % T;
+    float sx = 0.f, sy = 0.f;
+    if (n <= kMergeList) {
+      for (int k = 0; k < n; ++k) {
+        const int ly = r + s_oy[k], lx = c + s_ox[k], P = s_pitch[k];
+        if (ly < P && lx < P) {
+          const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
           sx += v.x;
           sy += v.y;
         }
       }
+    } else {  // long lists: same order, read from global memory
+      for (int dy = 0; dy <= halo; ++dy) {
+        int sty = ty - dy;
+        while (sty < 0) sty += nty;
+        for (int dx = 0; dx <= halo; ++dx) {
+          int stx = tx - dx;
+          while (stx < 0) stx += ntx;
+          const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
+          const int ly = r + dy * T, lx = c + dx * T;
+          for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
+            const TileEntry te = ent[k];
+            if (ly < te.pitch && lx < te.pitch) {
+              const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+              sx += v.x;
+              sy += v.y;
+            }
+          }
+        }
+      }
     }
+    out[(int64_t)(ty * T + r) * Kx + tx * T + c] = make_float2(sx, sy);
   }
-  grid[(int64_t)l * Ky * Kx + e] = make_float2(sx, sy);
 }
 
 // Per-block FP64 norms from the item partials (fixed order), then the
@@ -645,31 +862,33 @@ hipError_t launch_colfft_inv(int Ky, const float2* grid, float2* half, const flo
 }
 
 template <int GP>
-static hipError_t gather_gp(int mode, const GArgs& a, float2* vis, const float2* y, double* norms, int it0,
-                            int it1, int nb, hipStream_t s) {
+static hipError_t gather_gp(int mode, const GArgs& a, float2* vis, const float2* y, double* norms, size_t lds,
+                            int it0, int it1, int nb, hipStream_t s) {
   if (mode == 0)
-    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64), 0, s, a, vis, y, norms, it0, it1);
+    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64), lds, s, a, vis, y, norms, it0, it1);
   else
-    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64), 0, s, a, vis, y, norms, it0, it1);
+    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64), lds, s, a, vis, y, norms, it0, it1);
   return hipGetLastError();
 }
 
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y, double* item_norms,
-                         int it0, int it1, int grid_blocks, hipStream_t s) {
+                         int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s) {
   const int n = it1 - it0;
   if (n <= 0) return hipSuccess;
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
+  const size_t lds = (size_t)max_pitch * max_pitch * sizeof(float2);
+  if (lds > 65536) return hipErrorInvalidValue;
   switch (gprec) {
-    case 0: return gather_gp<0>(mode, a, vis, y, item_norms, it0, it1, nb, s);
-    case 1: return gather_gp<1>(mode, a, vis, y, item_norms, it0, it1, nb, s);
-    case 2: return gather_gp<2>(mode, a, vis, y, item_norms, it0, it1, nb, s);
+    case 0: return gather_gp<0>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
+    case 1: return gather_gp<1>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
+    case 2: return gather_gp<2>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int GP>
-static hipError_t scatter_gp(int mode, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0,
-                             int it1, int nb, hipStream_t s) {
+static hipError_t scatter_gp(int mode, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0, int it1,
+                             int nb, hipStream_t s) {
   if (mode == 0)
     hipLaunchKernelGGL((k_scatter<GP, 0>), dim3(nb), dim3(64), lds, s, a, vis, partials, it0, it1);
   else
@@ -694,9 +913,9 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
                         int Ky, int Kx, int T, int halo, int l0, int nl, hipStream_t s) {
-  const int64_t cells = (int64_t)Ky * Kx;
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)((cells + 255) / 256), nl), dim3(256), 0, s, grid, partials,
-                     tile_ptr, entries, Ky, Kx, T, halo, l0);
+  const int tiles = (Ky / T) * (Kx / T);
+  hipLaunchKernelGGL(k_merge, dim3(tiles, nl), dim3(256), 0, s, grid, partials, tile_ptr, entries, Ky, Kx, T, halo,
+                     l0);
   return hipGetLastError();
 }
 

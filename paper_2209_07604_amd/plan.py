@@ -95,6 +95,14 @@ class Plan:
         L.check(self._lib.phi_plan_load_g(self._h, int(block), _ptr(w), kind, _stream(torch, self.device)),
                 "phi_plan_load_g")
 
+    def set_flags(self, flags):
+        L.check(self._lib.phi_plan_set_flags(self._h, int(flags)), "phi_plan_set_flags")
+
+    def set_tuning(self, tile, persist_blocks=0):
+        import torch
+        L.check(self._lib.phi_plan_set_tuning(self._h, int(tile), int(persist_blocks), _stream(torch, self.device)),
+                "phi_plan_set_tuning")
+
     def set_theta(self, theta):
         import torch
         t = np.ascontiguousarray(theta, dtype=np.float64)

@@ -181,6 +181,41 @@ def test_launch_forms_bitwise_equal(mode):
             assert np.array_equal(grad.cpu().numpy().astype(np.float64), a[1])
 
 
+@pytest.mark.parametrize("tile,persist", [(16, 0), (32, 301), (64, 0)])
+def test_tuning_choices_match_oracle(tile, persist):
+    """Every tile edge and launch shape the autotuner may pick is exact."""
+    _say("[tuning]", tile, persist)
+    c = case("C3s")
+    plan = c.plan()
+    plan.set_tuning(tile, persist)
+    Vp_o, grad_o, rho_o, res_o = __import__("oracle").dual_step(
+        c.op, {l: x.astype(np.float64) for l, x in c.Xt.items()}, c.V, c.Y, c.eps, None)
+    got = gpu_dual(c, plan, c.V, c.eps, None)
+    assert rel_l2(np.concatenate(got[0]), np.concatenate(Vp_o)) <= 1e-5
+    assert rel_l2(got[2], rho_o) <= 1e-5
+    for l in range(c.prob.L):
+        assert rel_l2(got[1][l], grad_o[l]) <= 1e-5
+    Xo = {l: x.astype(np.float64) for l, x in c.X.items()}
+    assert rel_l2(np.concatenate(gpu_forward(c, plan)), np.concatenate(c.op.forward(Xo))) <= 1e-5
+
+
+def test_autotune_keeps_results():
+    c = case("C2s")
+    plan = c.plan()
+    ref = gpu_dual(c, plan, c.V, c.eps, None)
+    assert plan.autotune(2) == 0
+    info = plan.info()
+    _say("[autotune] tile", info["tile"], "persist", info["persist_blocks"])
+    got = gpu_dual(c, plan, c.V, c.eps, None)
+    Vp_o, grad_o, rho_o, res_o = __import__("oracle").dual_step(
+        c.op, {l: x.astype(np.float64) for l, x in c.Xt.items()}, c.V, c.Y, c.eps, None)
+    assert rel_l2(np.concatenate(got[0]), np.concatenate(Vp_o)) <= 1e-5
+    for l in range(c.prob.L):
+        assert rel_l2(got[1][l], grad_o[l]) <= 1e-5
+    # a different tiling regroups the FP32 window sums: equal up to rounding
+    assert rel_l2(got[2], ref[2]) <= 1e-6
+
+
 def test_determinism_and_permutation_roundtrip():
     c = case("C3s")
     plan = c.plan()
