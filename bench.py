@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--forms", default="plain_c64,batched_c64,batched_f16,batched_bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="fix the tile edge (skips the autotuner)")
+    ap.add_argument("--persist", type=int, default=0, help="persistent G-stage grid with --tile")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the data-fidelity step shards by channel with no exchange, "
@@ -180,7 +184,9 @@ def main():
         grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
         rho = torch.empty(nblk, dtype=torch.float64, device=dev)
         res = torch.empty(nblk, dtype=torch.float64, device=dev)
-        if kind == "batched" and not args.no_autotune:
+        if kind == "batched" and args.tile:
+            p.set_tuning(args.tile, args.persist)
+        elif kind == "batched" and not args.no_autotune:
             rc = p.autotune(3)
             log("[bench] autotune %s -> rc %d, tile %d, persist %d" % (
                 prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
@@ -221,6 +227,15 @@ def main():
         log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
             form, ms, M / (ms * 1e-3), {k_: round(v_ / max(calls, 1), 3) for k_, v_ in stages.items()}))
 
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("[bench] calibration copy of %d MiB done" % args.calib_copy_mib)
+        del src, dst
     head = "batched_f16" if "batched_f16" in results else forms[-1]
     r = results[head]
     info = r["info"]

@@ -7,7 +7,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libphi.so")
+LIB_PATH = os.environ.get("PHI_LIB") or os.path.join(HERE, "libphi.so")
 
 PHI_OK = 0
 STATUS = {

@@ -18,30 +18,31 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
     """Compile every source into libphi.so (always recompiles)."""
     objs = []
+    lib = out or LIB
     for src in SOURCES:
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+        obj = os.path.join(os.path.dirname(lib), os.path.basename(lib) + "." + os.path.basename(src) + ".o")
         cmd = [hipcc(), "-c", "-fPIC", "-O3", "-std=c++17", "--offload-arch=" + ARCH,
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
                "-Wall", "-Wno-unused-function",
-               "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj]
+               "-I", os.path.join(ROOT, "include"), "-I", CSRC, src, "-o", obj] + ["-D" + d for d in defines]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
 
 
 if __name__ == "__main__":

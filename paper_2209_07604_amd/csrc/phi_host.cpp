@@ -37,6 +37,7 @@ inline uint32_t spread_bits(uint32_t v) {  // 13 bits -> even positions
 }
 // Z-order key of a window origin: any aligned power-of-two tile of the grid
 // is one contiguous run of keys, so one sort serves every tile size.
+// (26 bits; the plan's sort key keeps bits 25..8 above the window size.)
 inline uint32_t morton(uint32_t by, uint32_t bx) { return (spread_bits(by) << 1) | spread_bits(bx); }
 
 inline int ilog2(int v) {
@@ -243,6 +244,13 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
       }
       it.v1 = (int32_t)v;
       it.ntap = (int32_t)taps;
+      {
+        const int n = it.v1 - it.v0, q = (n + kGatherWaves - 1) / kGatherWaves;
+        for (int w = 1; w < kGatherWaves; ++w) {
+          const int64_t m = std::min<int64_t>(it.v0 + (int64_t)w * q, it.v1);
+          it.sub[w - 1] = (int32_t)(p->tap_off[m] - it.tap0);
+        }
+      }
       it.pitch = T + smax - 1;
       it.poff = poff;
       poff += (int64_t)it.pitch * it.pitch;
@@ -394,7 +402,12 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
       keys.resize(n);
       for (int64_t i = 0; i < n; ++i) {
         const int64_t m = u0 + i;
-        keys[i] = ((uint64_t)morton((uint32_t)d->h_base[2 * m], (uint32_t)d->h_base[2 * m + 1]) << 32) | (uint64_t)i;
+        // Z-order of the 16 x 16 sub-tile, then window size, then the Z-order
+        // inside the sub-tile: aligned tiles of 16, 32, 64 stay contiguous and
+        // each sub-tile holds runs of equal S
+        const uint32_t mo = morton((uint32_t)d->h_base[2 * m], (uint32_t)d->h_base[2 * m + 1]);
+        const uint32_t key = ((mo >> 8) << 13) | ((uint32_t)d->h_stencil[m] << 8) | (mo & 0xFFu);
+        keys[i] = ((uint64_t)key << 32) | (uint64_t)i;
       }
       std::sort(keys.begin(), keys.end());
       for (int64_t i = 0; i < n; ++i) {

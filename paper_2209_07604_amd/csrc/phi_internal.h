@@ -29,8 +29,15 @@ struct Item {
   int32_t ty0, tx0;
   int32_t pitch;
   int32_t ntap;    // taps of the run (sum of S^2)
+  int32_t sub[3];  // taps before visibility v0 + w * ceil(n / W), w = 1..3
+                   // (where the gather's waves 1..3 start, W <= 4 waves)
+  int32_t pad;
 };
-static_assert(sizeof(Item) == 48, "Item layout");
+static_assert(sizeof(Item) == 64, "Item layout");
+#ifndef PHI_GATHER_WAVES
+#define PHI_GATHER_WAVES 4
+#endif
+constexpr int kGatherWaves = PHI_GATHER_WAVES;
 
 // Merge-list entry: one tile partial that overlaps a tile.
 struct TileEntry {

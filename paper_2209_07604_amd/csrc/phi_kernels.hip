@@ -65,10 +65,11 @@ __device__ __forceinline__ float readlane_f(float v, int i) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
 
-// ceil(65536 / S): (t * r) >> 16 == t / S exactly for t < 441, S <= 21
-__constant__ uint32_t c_recip[kMaxS + 1] = {
-    0,     65536, 32768, 21846, 16384, 13108, 10923, 9363, 8192, 7282, 6554,
-    5958,  5462,  5042,  4682,  4370,  4096,  3856,  3641, 3450, 3277, 3121};
+// Row and column of tap t of an S x S window: i = floor((t + 1/2) / S) in
+// FP32 with the hardware reciprocal is exact for t < 441, S <= 21 (the
+// quotient stays >= 1/(2S) away from an integer, the reciprocal's relative
+// error is ~1e-7), so no table or integer division is needed.
+__device__ __forceinline__ int tap_row(int t, float rS) { return (int)(((float)t + 0.5f) * rS); }
 
 // Spread consecutive panels over one XCD: work-group i runs on XCD i % 8.
 __device__ __forceinline__ int xcd_remap(int i, int n) {
@@ -375,19 +376,25 @@ __device__ __forceinline__ uint32_t meta_at(uint32_t mcur, uint32_t mnxt, int of
 // from LDS and only G streams through the vector memory path.  Lane i of
 // each chunk keeps visibility i's result: the residual, its FP64 norms and
 // the stores are lane-parallel and coalesced.
-template <int NK>
+// windows prefetched per wave for windows of NK 64-tap steps (about 24
+// registers of G taps in flight for 32-bit taps, half as deep for complex64)
+#ifndef PHI_DEPTH_REGS
+#define PHI_DEPTH_REGS 16
+#endif
+template <int GP, int NK>
 struct Depth {
-  static constexpr int value = NK == 1 ? 12 : NK == 2 ? 6 : NK <= 4 ? 4 : 3;
+  static constexpr int regs = GP == 0 ? PHI_DEPTH_REGS / 2 : PHI_DEPTH_REGS;
+  static constexpr int value = regs / NK < 2 ? 2 : regs / NK;
 };
 
 template <int GP, int MODE, int NK, int D>
-__device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, float2* __restrict__ vis,
-                                            const float2* __restrict__ yv, double& rho2, double& res2,
-                                            const float2* __restrict__ tile) {
+__device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
+                                            float2* __restrict__ vis, const float2* __restrict__ yv,
+                                            double& rho2, double& res2, const float2* __restrict__ tile) {
   using R = typename GRaw<GP>::T;
   const R* __restrict__ G = static_cast<const R*>(a.G);
-  const int lane = threadIdx.x;
-  const int v0 = item.v0, v1 = item.v1, vlast = v1 - 1, P = item.pitch;
+  const int lane = threadIdx.x & 63;
+  const int vlast = v1 - 1, P = item.pitch;
   const float th = a.theta[item.blk];
   float inv_sig = 1.f;
   if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
@@ -401,21 +408,33 @@ __device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, fl
   }
   R gb[D][NK];
   uint32_t ms[D];
-  int64_t tapf = item.tap0;
+  int64_t tapf = tap0;
   int jf = v0;
+  // per-lane tap index clamped to the window, kept for runs of equal S
+  int fS = -1;
+  int ft[NK];
   auto fetch = [&](R(&g)[NK], uint32_t& m) {
     const bool live = jf < v1;
     const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
     m = mt;
     const int S = 2 * (int)(mt >> 26) + 1;
-    const int S2 = S * S;
-    const int64_t tb = live ? tapf : item.tap0;
+    if (S != fS) {
+      fS = S;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) g[k] = G[tb + min(k * 64 + lane, S2 - 1)];
-    tapf += live ? S2 : 0;
+      for (int k = 0; k < NK; ++k) ft[k] = min(k * 64 + lane, S * S - 1);
+    }
+    const R* __restrict__ gp = G + (live ? tapf : tap0);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) g[k] = gp[ft[k]];
+    tapf += live ? S * S : 0;
     ++jf;
   };
   float2 res = make_float2(0.f, 0.f);
+  // per-lane LDS offset (row * P + column) of each tap step, kept for runs of
+  // equal S; lanes past the window read a valid cell and add zero
+  int pS = -1;
+  int off[NK];
+  uint32_t live_mask = 0;
   auto flush = [&]() {
     if (cb + lane < v1) {
       if (MODE == 0) {
@@ -443,17 +462,27 @@ __device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, fl
     }
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
-    const uint32_t rS = c_recip[S];
+    if (S != pS) {
+      pS = S;
+      const float rS = __builtin_amdgcn_rcpf((float)S);
+      live_mask = 0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t0 = k * 64 + lane;
+        const int t = min(t0, S2 - 1);
+        const int ii = tap_row(t, rS);
+        off[k] = ii * P + (t - ii * S);
+        live_mask |= (t0 < S2 ? 1u : 0u) << k;
+      }
+    }
     const int base = (by - item.ty0) * P + (bx - item.tx0);
     float ax = 0.f, ay = 0.f;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = k * 64 + lane;
-      if (t < S2) {
-        const int ii = (int)(((uint32_t)t * rS) >> 16);
-        const int jj = t - ii * S;
-        const float2 gg = unpack_g<GP>(g[k]);
-        const float2 X = tile[base + ii * P + jj];
+      if (k * 64 < S2) {
+        float2 gg = unpack_g<GP>(g[k]);
+        if (!(live_mask & (1u << k))) gg = make_float2(0.f, 0.f);
+        const float2 X = tile[base + off[k]];
         ax += gg.x * X.x - gg.y * X.y;
         ay += gg.x * X.y + gg.y * X.x;
       }
@@ -477,17 +506,22 @@ __device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, fl
   if (cb < v1) flush();
 }
 
+// kGatherWaves waves per work-group share one LDS copy of the item's grid
+// region; wave w takes the w-th quarter of the item's visibilities.
 template <int GP, int MODE>
-__global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis, const float2* __restrict__ yv,
-                                               double* __restrict__ item_norms, int it0, int it1) {
+__global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* __restrict__ vis,
+                                                              const float2* __restrict__ yv,
+                                                              double* __restrict__ item_norms, int it0, int it1) {
   extern __shared__ float2 tile[];
-  const int lane = threadIdx.x;
+  __shared__ double s_norm[2 * kGatherWaves];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
     const Item item = a.items[it];
     const int P = item.pitch;
     // copy the item's grid region (rows ty0.., columns tx0.., wrapped)
     const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
-    for (int e = lane; e < P * P; e += 64) {
+    for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
       const int r = e / P, c = e - (e / P) * P;
       int gr = item.ty0 + r, gc = item.tx0 + c;
       gr -= (gr >= a.Ky) ? a.Ky : 0;
@@ -495,24 +529,47 @@ __global__ __launch_bounds__(64) void k_gather(GArgs a, float2* __restrict__ vis
       tile[e] = grid[(size_t)gr * a.Kx + gc];
     }
     __syncthreads();
+    const int n = item.v1 - item.v0, q = (n + kGatherWaves - 1) / kGatherWaves;
+    const int wv0 = min(item.v0 + w * q, item.v1), wv1 = min(item.v0 + (w + 1) * q, item.v1);
+    const int64_t wtap =
+        item.tap0 + (w == 0 ? 0 : w == 1 ? item.sub[0] : w == 2 ? item.sub[1] : item.sub[2]);
     const int smax = P - a.T + 1;
     const int nk = (smax * smax + 63) / 64;
     double rho2 = 0.0, res2 = 0.0;
-    switch (nk) {
-      case 1: gather_item<GP, MODE, 1, Depth<1>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      case 2: gather_item<GP, MODE, 2, Depth<2>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      case 3: gather_item<GP, MODE, 3, Depth<3>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      case 4: gather_item<GP, MODE, 4, Depth<4>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      case 5: gather_item<GP, MODE, 5, Depth<5>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      case 6: gather_item<GP, MODE, 6, Depth<6>::value>(a, item, vis, yv, rho2, res2, tile); break;
-      default: gather_item<GP, MODE, 7, Depth<7>::value>(a, item, vis, yv, rho2, res2, tile); break;
+    if (wv0 < wv1) {
+      switch (nk) {
+#define PHI_G_CASE(K)                                                                                       \
+  case K:                                                                                                   \
+    gather_item<GP, MODE, K, Depth<GP, K>::value>(a, item, wv0, wv1, wtap, vis, yv, rho2, res2, tile); \
+    break;
+        PHI_G_CASE(1)
+        PHI_G_CASE(2)
+        PHI_G_CASE(3)
+        PHI_G_CASE(4)
+        PHI_G_CASE(5)
+        PHI_G_CASE(6)
+        default:
+          gather_item<GP, MODE, 7, Depth<GP, 7>::value>(a, item, wv0, wv1, wtap, vis, yv, rho2, res2, tile);
+          break;
+#undef PHI_G_CASE
+      }
     }
     if (MODE == 1) {
       rho2 = wave_sum_d(rho2);
       res2 = wave_sum_d(res2);
       if (lane == 0) {
-        item_norms[2 * (int64_t)it] = rho2;
-        item_norms[2 * (int64_t)it + 1] = res2;
+        s_norm[2 * w] = rho2;
+        s_norm[2 * w + 1] = res2;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double r0 = 0.0, r1 = 0.0;
+        for (int k = 0; k < kGatherWaves; ++k) {
+          r0 += s_norm[2 * k];
+          r1 += s_norm[2 * k + 1];
+        }
+        item_norms[2 * (int64_t)it] = r0;
+        item_norms[2 * (int64_t)it + 1] = r1;
       }
     }
     __syncthreads();
@@ -552,18 +609,27 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
   uint32_t ms[D];
   int64_t tapf = item.tap0;
   int jf = v0;
+  int fS = -1;
+  int ft[NK];
   auto fetch = [&](R(&g)[NK], uint32_t& m) {
     const bool live = jf < v1;
     const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
     m = mt;
     const int S = 2 * (int)(mt >> 26) + 1;
-    const int S2 = S * S;
-    const int64_t tb = live ? tapf : item.tap0;
+    if (S != fS) {
+      fS = S;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) g[k] = G[tb + min(k * 64 + lane, S2 - 1)];
-    tapf += live ? S2 : 0;
+      for (int k = 0; k < NK; ++k) ft[k] = min(k * 64 + lane, S * S - 1);
+    }
+    const R* __restrict__ gp = G + (live ? tapf : item.tap0);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) g[k] = gp[ft[k]];
+    tapf += live ? S * S : 0;
     ++jf;
   };
+  int pS = -1;
+  int off[NK];
+  uint32_t live_mask = 0;
   auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
     if (i == cb + 64) {
       cb += 64;
@@ -574,21 +640,34 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
     }
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
-    const uint32_t rS = c_recip[S];
+    if (S != pS) {
+      pS = S;
+      const float rS = __builtin_amdgcn_rcpf((float)S);
+      live_mask = 0;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) {
+        const int t0 = k * 64 + lane;
+        const int t = min(t0, S2 - 1);
+        const int ii = tap_row(t, rS);
+        off[k] = ii * P + (t - ii * S);
+        live_mask |= (t0 < S2 ? 1u : 0u) << k;
+      }
+    }
     const float vx = readlane_f(avc.x, i - cb), vy = readlane_f(avc.y, i - cb);
     const int base = (by - item.ty0) * P + (bx - item.tx0);
+    // all steps of one window touch distinct cells: read them all, then add
+    // and write, so the window costs one LDS round trip, not one per step
+    float2 cur[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (k * 64 < S2 && (live_mask & (1u << k))) cur[k] = acc[base + off[k]];
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      const int t = k * 64 + lane;
-      if (t < S2) {
-        const int ii = (int)(((uint32_t)t * rS) >> 16);
-        const int jj = t - ii * S;
+      if (k * 64 < S2 && (live_mask & (1u << k))) {
         const float2 gg = unpack_g<GP>(g[k]);
-        float2* p = &acc[base + ii * P + jj];
-        float2 cur = *p;
-        cur.x += gg.x * vx + gg.y * vy;
-        cur.y += gg.x * vy - gg.y * vx;
-        *p = cur;
+        cur[k].x += gg.x * vx + gg.y * vy;
+        cur[k].y += gg.x * vy - gg.y * vx;
+        acc[base + off[k]] = cur[k];
       }
     }
   };
@@ -620,13 +699,13 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
     const int smax = P - a.T + 1;
     const int nk = (smax * smax + 63) / 64;
     switch (nk) {
-      case 1: scatter_item<GP, MODE, 1, Depth<1>::value>(a, item, vis, acc); break;
-      case 2: scatter_item<GP, MODE, 2, Depth<2>::value>(a, item, vis, acc); break;
-      case 3: scatter_item<GP, MODE, 3, Depth<3>::value>(a, item, vis, acc); break;
-      case 4: scatter_item<GP, MODE, 4, Depth<4>::value>(a, item, vis, acc); break;
-      case 5: scatter_item<GP, MODE, 5, Depth<5>::value>(a, item, vis, acc); break;
-      case 6: scatter_item<GP, MODE, 6, Depth<6>::value>(a, item, vis, acc); break;
-      default: scatter_item<GP, MODE, 7, Depth<7>::value>(a, item, vis, acc); break;
+      case 1: scatter_item<GP, MODE, 1, Depth<GP, 1>::value>(a, item, vis, acc); break;
+      case 2: scatter_item<GP, MODE, 2, Depth<GP, 2>::value>(a, item, vis, acc); break;
+      case 3: scatter_item<GP, MODE, 3, Depth<GP, 3>::value>(a, item, vis, acc); break;
+      case 4: scatter_item<GP, MODE, 4, Depth<GP, 4>::value>(a, item, vis, acc); break;
+      case 5: scatter_item<GP, MODE, 5, Depth<GP, 5>::value>(a, item, vis, acc); break;
+      case 6: scatter_item<GP, MODE, 6, Depth<GP, 6>::value>(a, item, vis, acc); break;
+      default: scatter_item<GP, MODE, 7, Depth<GP, 7>::value>(a, item, vis, acc); break;
     }
     __syncthreads();
     float2* out = partials + item.poff;
@@ -865,9 +944,9 @@ template <int GP>
 static hipError_t gather_gp(int mode, const GArgs& a, float2* vis, const float2* y, double* norms, size_t lds,
                             int it0, int it1, int nb, hipStream_t s) {
   if (mode == 0)
-    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64), lds, s, a, vis, y, norms, it0, it1);
+    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64 * kGatherWaves), lds, s, a, vis, y, norms, it0, it1);
   else
-    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64), lds, s, a, vis, y, norms, it0, it1);
+    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64 * kGatherWaves), lds, s, a, vis, y, norms, it0, it1);
   return hipGetLastError();
 }
 
