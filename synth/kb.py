@@ -1,7 +1,7 @@
 """Kaiser-Bessel interpolation kernel used to build the rows of G.
 
 The paper builds G from a compact-support non-uniform Fourier interpolation
-kernel following Fessler & Sutton's NUFFT (Section 2.1, eq. 1) and leaves the
+kernel following the NUFFT of Fessler & Sutton (Section 2.1, eq. 1) and leaves the
 kernel type and width to a parameter file.  The generator uses the
 Kaiser-Bessel kernel of width J = 7 on a 2x oversampled grid, with the shape
 parameter of Beatty, Nishimura & Pauly (2005):

@@ -10,11 +10,11 @@ Recipes (stand-ins for the VLA Cyg A data of Section 5, which is not used):
     [1e-3, 1]) plus one extended blob (white noise smoothed by a Gaussian of
     sigma = 8 px, clipped at 0, inside an ellipse); channel l is
     x_ref * (nu_l / nu_0)^(-alpha(p)) with a smooth spectral-index map
-    alpha in [0.5, 1] (power-law spectra as in Section 5's spectral analysis).
+    alpha in [0.5, 1] (power-law spectra, as in the spectral analysis of Section 6.2).
   * uv: omega ~ N(0, (pi/4)^2 I) rejection-sampled into [-pi, pi)^2 (radially
     concentrated); for wideband configurations one reference draw is scaled by
     nu_l / nu_max per channel.  Blocks split a channel by |omega| quantiles
-    (inner/outer, as the A/C configuration split of Section 5).
+    (inner/outer, as the A/C configuration blocks of Section 6.1).
   * w-projection: w ~ U[0, w_max]; the per-axis w-kernel half-width is
     a = 5 w / w_max cells, S_w = 1 + 2 round(a); the window is the
     7-tap Kaiser-Bessel vector convolved with the S_w-tap kernel per axis
