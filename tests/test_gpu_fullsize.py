@@ -1,0 +1,126 @@
+"""Full-size parity: the 16-channel x 4-block, 1024^2, 1.5M-visibility-per-channel
+workload (w-stencils 7..17) in the launch configuration bench.py times
+(batched, hipGraph replay, tile 16), checked against the FP64 oracle on every
+output of two whole channels (the lowest and highest frequency): v+, grad,
+rho and r of all their blocks.  Complex64 G must match to 1e-5, FP16 G to 2e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from _cases import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+CHECK = (0, 15)
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def full():
+    import oracle
+    import synth
+    from oracle.dual import block_radii
+    prob = synth.make_problem("C2")
+    s_y, s_x = prob.deapodisation()
+    blocks, exact = [], {}
+    for k, (l, b) in enumerate(prob.block_list()):
+        blk = prob.block(l, b)
+        if l in CHECK:
+            w, off = blk.windows(np.complex128)
+            exact[k] = (blk, w, off)
+            blocks.append((blk.base, blk.S, w.astype(np.complex64)))
+        else:
+            w, off = blk.windows(np.complex64)
+            blocks.append((blk.base, blk.S, w))
+        if k % 16 == 0:
+            _say("[fullsize] generated block", k)
+    # theta from the oracle's clean power on the checked channels (30 dB); 1 elsewhere
+    theta = np.ones(len(blocks))
+    X = {l: prob.image(l).astype(np.float64) for l in CHECK}
+    ops = {}
+    for l in CHECK:
+        ks = [k for k in exact if prob.block_list()[k][0] == l]
+        op1 = oracle.Operator(prob.Ny, prob.Nx, s_y, s_x,
+                              [oracle.BlockG(l, 1.0, oracle.g_matrix(exact[k][0].base, exact[k][0].S, exact[k][1],
+                                                                      exact[k][2], prob.Ky, prob.Kx))
+                               for k in ks])
+        y0 = op1.forward(X)
+        pw = sum(float(np.vdot(y, y).real) for y in y0) / sum(len(y) for y in y0)
+        th = 1.0 / np.sqrt(pw * 1e-3)
+        for k in ks:
+            theta[k] = th
+        ops[l] = (ks, op1, y0)
+        _say("[fullsize] oracle channel", l, "ready")
+    rng = np.random.default_rng(np.random.SeedSequence((220907604, 88)))
+    Y, V = [], []
+    for k, (base, S, w) in enumerate(blocks):
+        n = len(S)
+        V.append(0.1 * (rng.standard_normal(n) + 1j * rng.standard_normal(n)))
+        noise = (rng.standard_normal(n) + 1j * rng.standard_normal(n)) / np.sqrt(2)
+        Y.append(noise)
+    for l, (ks, op1, y0) in ops.items():
+        for k, y in zip(ks, y0):
+            Y[k] = theta[k] * y + Y[k]
+    eps = np.concatenate([block_radii(nv) for nv in prob.n_vis])
+    return dict(prob=prob, blocks=blocks, exact=exact, theta=theta, ops=ops, Y=Y, V=V, eps=eps, s_y=s_y, s_x=s_x)
+
+
+def _oracle_dual(F, l):
+    import oracle
+    prob, exact, theta = F["prob"], F["exact"], F["theta"]
+    ks = F["ops"][l][0]
+    op = oracle.Operator(prob.Ny, prob.Nx, F["s_y"], F["s_x"],
+                         [oracle.BlockG(l, theta[k], oracle.g_matrix(exact[k][0].base, exact[k][0].S, exact[k][1],
+                                                                     exact[k][2], prob.Ky, prob.Kx, theta[k]))
+                          for k in ks])
+    Xt = {l: 0.5 * prob.image(l).astype(np.float64)}
+    return ks, oracle.dual_step(op, Xt, [F["V"][k] for k in ks], [F["Y"][k] for k in ks], F["eps"][ks])
+
+
+@pytest.fixture(scope="module")
+def oracle_results(full):
+    return {l: _oracle_dual(full, l) for l in CHECK}
+
+
+@pytest.mark.parametrize("prec,tol", [("c64", 1e-5), ("f16", 2e-3)])
+def test_fullsize_dual_step(full, oracle_results, prec, tol):
+    from paper_2209_07604_amd import Plan, GRAPH
+    prob, blocks = full["prob"], full["blocks"]
+    n_vis = [len(S) for (_, S, _) in blocks]
+    base = np.concatenate([b for (b, _, _) in blocks])
+    S = np.concatenate([s for (_, s, _) in blocks])
+    plan = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, full["s_y"], full["s_x"], full["theta"],
+                g_prec=prec, flags=GRAPH)
+    for k, (_, _, w) in enumerate(blocks):
+        plan.load_g(k, w)
+    plan.set_tuning(16, 0)
+    _say("[fullsize] plan", prec, plan.info())
+    xt = torch.from_numpy(np.stack([0.5 * prob.image(l) for l in range(prob.L)]).astype(np.float32)).cuda()
+    v = plan.to_plan(torch.from_numpy(np.concatenate(full["V"]).astype(np.complex64)).cuda())
+    y = plan.to_plan(torch.from_numpy(np.concatenate(full["Y"]).astype(np.complex64)).cuda())
+    eps = torch.from_numpy(full["eps"]).cuda()
+    grad, rho, res = plan.dual_step(xt, v, y, eps)
+    vp = plan.from_plan(v).cpu().numpy().astype(np.complex128)
+    torch.cuda.synchronize()
+    plan.check()
+    grad = grad.cpu().numpy().astype(np.float64)
+    rho, res = rho.cpu().numpy(), res.cpu().numpy()
+    starts = np.concatenate([[0], np.cumsum(n_vis)])
+    for l in CHECK:
+        ks, (Vp_o, grad_o, rho_o, res_o) = oracle_results[l]
+        got_v = np.concatenate([vp[starts[k]:starts[k + 1]] for k in ks])
+        e_v = rel_l2(got_v, np.concatenate(Vp_o))
+        e_g = rel_l2(grad[l], grad_o[l])
+        e_rho = rel_l2(rho[ks], rho_o)
+        e_res = rel_l2(res[ks], res_o)
+        _say("[fullsize] %s channel %d: rel L2 v+ %.2e grad %.2e rho %.2e res %.2e (rho/eps %s)" % (
+            prec, l, e_v, e_g, e_rho, e_res, np.round(rho_o / full["eps"][ks], 2)))
+        assert np.all(rho_o > full["eps"][ks])
+        assert e_v <= tol and e_g <= tol and e_rho <= tol and e_res <= tol
