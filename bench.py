@@ -70,32 +70,59 @@ def generate(name, log_every=8):
     return prob, blocks
 
 
-def cpu_baseline(prob, budget_s=30.0):
+def cpu_baseline(prob, plan, theta, budget_s=30.0):
     """The FP64 oracle's dual step on channel 0 of the same workload, timed on
-    the host cores (numpy/scipy as they stand)."""
+    the host cores (numpy/scipy as they stand).  The same inputs then go
+    through the headline GPU plan, and its channel-0 outputs are compared with
+    the oracle's (error of the timed form against FP64)."""
+    import torch
     import oracle
     from oracle.dual import block_radii
     t_setup = time.time()
-    sel = [(0, b) for b in range(prob.n_blocks[0])]
+    nb0 = prob.n_blocks[0]
+    sel = [(0, b) for b in range(nb0)]
     rng = np.random.default_rng(5)
-    op = oracle.Operator.from_problem(prob, None, blocks=sel)
+    op = oracle.Operator.from_problem(prob, {k: theta[i] for i, k in enumerate(sel)}, blocks=sel)
     x = prob.image(0).astype(np.float64)
     Y = op.forward({0: x})
     V = [0.1 * (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
-    Y = [y + (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
+    Y = [y + (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) / np.sqrt(2) for y in Y]
     eps = block_radii(prob.n_vis[0])
     log("[bench] cpu baseline set-up %.1f s" % (time.time() - t_setup))
     n, t_tot = 0, 0.0
     while n == 0 or (t_tot < budget_s / 3 and n < 3):
         t0 = time.perf_counter()
-        oracle.dual_step(op, {0: 0.5 * x}, V, Y, eps)
+        Vp_o, grad_o, rho_o, res_o = oracle.dual_step(op, {0: 0.5 * x}, V, Y, eps)
         t_tot += time.perf_counter() - t0
         n += 1
     m = int(sum(prob.n_vis[0]))
-    return {"value": m * n / t_tot, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
+    base = {"value": m * n / t_tot, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
             "sample": "channel 0 (%d blocks, %d visibilities, %dx%d grid) of the same workload, FP64 "
                       "numpy/scipy dual step, %d run(s), %.2f s each; numpy.fft and scipy.sparse run "
-                      "single-threaded" % (len(sel), m, prob.Ky, prob.Kx, n, t_tot / n)}
+                      "single-threaded" % (nb0, m, prob.Ky, prob.Kx, n, t_tot / n)}
+    # the same channel-0 inputs through the GPU plan (other channels: zero data)
+    M = plan.M
+    vh = np.zeros(M, np.complex64)
+    yh = np.zeros(M, np.complex64)
+    vh[:m] = np.concatenate(V)
+    yh[:m] = np.concatenate(Y)
+    dev = plan.device
+    xt = torch.zeros((plan.L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
+    xt[0] = torch.from_numpy((0.5 * x).astype(np.float32))
+    v = plan.to_plan(torch.from_numpy(vh).to(dev))
+    y = plan.to_plan(torch.from_numpy(yh).to(dev))
+    e_all = np.ones(plan.nblk)
+    e_all[:nb0] = eps
+    grad, rho, res = plan.dual_step(xt, v, y, torch.from_numpy(e_all).to(dev))
+    vp = plan.from_plan(v).cpu().numpy()[:m].astype(np.complex128)
+    g0 = grad[0].cpu().numpy().astype(np.float64)
+    r0 = rho.cpu().numpy()[:nb0]
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err = {"v_plus": rel(vp, np.concatenate(Vp_o)), "grad": rel(g0, grad_o[0]), "rho": rel(r0, rho_o),
+           "sample": "channel 0, all %d blocks, same inputs as the cpu baseline" % nb0}
+    return base, err
 
 
 def main():
@@ -273,10 +300,9 @@ def main():
     if "plain_c64" in results:
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
     if not args.no_cpu_baseline:
-        try:
-            line["cpu_baseline"] = cpu_baseline(prob)
-        except MemoryError:
-            line["cpu_baseline"] = None
+        hp = plans[head.split("_")[1]]
+        hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0))
+        line["cpu_baseline"], line["err_vs_fp64_" + head] = cpu_baseline(prob, hp, theta)
     print(json.dumps(line), flush=True)
 
 

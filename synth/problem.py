@@ -155,6 +155,29 @@ class Problem:
             out = np.concatenate([out, d[ok]])
         return out[:M]
 
+    def _track_omega(self, M):
+        """Earth-rotation tracks of a 27-antenna Y array (VLA-like): 351
+        baselines sampled over hour angles [-4 h, 4 h] at declination
+        +40.7 deg (the Cyg A phase centre of Section 5.1), scaled so the
+        longest projected baseline reaches |omega| = 0.9 pi."""
+        rng = self.rng(20_003)
+        lat, dec = np.deg2rad(34.08), np.deg2rad(40.73)
+        arms = np.deg2rad([5.0, 125.0, 245.0]) + rng.uniform(-0.02, 0.02, 3)
+        d = (np.arange(1, 10) / 9.0) ** 1.716
+        ant_e = np.concatenate([d * np.sin(a) for a in arms])
+        ant_n = np.concatenate([d * np.cos(a) for a in arms])
+        i, j = np.triu_indices(27, 1)
+        E, N = ant_e[j] - ant_e[i], ant_n[j] - ant_n[i]
+        Lx, Ly, Lz = -np.sin(lat) * N, E, np.cos(lat) * N
+        nt = -(-M // len(E))
+        H = np.linspace(-np.pi / 3, np.pi / 3, nt)
+        sH, cH = np.sin(H)[None, :], np.cos(H)[None, :]
+        u = sH * Lx[:, None] + cH * Ly[:, None]
+        v = -np.sin(dec) * cH * Lx[:, None] + np.sin(dec) * sH * Ly[:, None] + np.cos(dec) * Lz[:, None]
+        r = np.hypot(u, v).max()
+        om = np.stack([v.ravel(), u.ravel()], axis=1) * (0.9 * np.pi / r)
+        return om[:M]
+
     def _channel_uv(self, l):
         """All uv points and w of channel l, grouped into blocks (list of index arrays)."""
         cache = self.__dict__.setdefault("_uv_cache", {})
@@ -165,7 +188,15 @@ class Problem:
 
     def _channel_uv_draw(self, l):
         Ml = int(sum(self.n_vis[l]))
-        if self.shared_uv:
+        if self.coverage == "tracks":
+            rng = self.rng(20_000)
+            Mref = max(int(sum(m)) for m in self.n_vis)
+            om = self._track_omega(Mref)[:Ml]
+            w = rng.uniform(0.0, 1.0, Mref)[:Ml]
+            scale = self.nu[l] / self.nu.max() if self.nu is not None else 1.0
+            om = om * scale
+            w = w * scale
+        elif self.shared_uv:
             rng = self.rng(20_000)
             Mref = max(int(sum(m)) for m in self.n_vis)
             om = self._gauss_omega(rng, Mref)[:Ml]
@@ -365,6 +396,14 @@ CONFIGS = {
                         nu=_wide(3, 3.979, 8.019)),
     "C5s": lambda: dict(cfg_id=105, Ny=256, Nx=256, L=2, n_blocks=[1] * 2,
                         n_vis=[[200_000]] * 2, nu=_wide(2, 3.979, 8.019)),
+    # C5 with VLA-like Earth-rotation tracks (the regime where gridding pays)
+    "C5t": lambda: dict(cfg_id=5, Ny=4096, Nx=4096, L=16, n_blocks=[1] * 16,
+                        n_vis=[[8_000_000]] * 16, nu=_wide(16, 3.979, 8.019), coverage="tracks"),
+    "C5ts": lambda: dict(cfg_id=106, Ny=128, Nx=128, L=2, n_blocks=[1] * 2,
+                         n_vis=[[60_000]] * 2, nu=_wide(2, 3.979, 8.019), coverage="tracks"),
+    "dr_tiny": lambda: dict(cfg_id=107, Ny=32, Nx=32, L=2, n_blocks=[2, 1],
+                            n_vis=[[300, 211], [400]], nu=_wide(2, 1.0, 2.0), coverage="tracks",
+                            w_max_cells=2.0, s_cap=11, n_sources=5),
 }
 
 
