@@ -209,6 +209,32 @@ phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
  * workspace.  Keeps the fastest; overwrites the grid buffers.  Synchronous. */
 phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
 
+/* ---------------------------------------------------------------------------
+ * Visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5) of one
+ * data block, computed on the host in FP64 (a plan-time step, like packing G):
+ *   H = G^H Theta^H Theta G, S = {p : H_pp > 0}, Lam_p = H_pp^(-1/2),
+ *   y' = Lam G^H Theta^H y, Phi' = Lam H F Z.
+ * Row p of Lam H is returned as a dense W x W window (W = 2 Smax - 1,
+ * Smax = largest window of the block, which must be <= 11) anchored at
+ * (p_y - Smax + 1, p_x - Smax + 1) mod K, rows sorted by cell index
+ * p = p_y * Kx + p_x.  Because H is Hermitian, (Lam H)^H = H Lam: feeding
+ * these windows, theta = 1 and y' to an ordinary plan gives Phi', its
+ * adjoint and the reduced dual step (with eps'^2 = M' + 2 sqrt(M')).
+ * Inputs are one block's arrays in the layout of phi_desc / phi_plan_load_g;
+ * h_y (complex128 [n_vis]) may be NULL (then y' = 0).  Host memory only.
+ */
+typedef struct phi_dr_s* phi_dr;
+phi_status phi_dr_create(int32_t ky, int32_t kx, int64_t n_vis, const int32_t* h_base, const uint8_t* h_stencil,
+                         const void* h_windows, int32_t host_type, double theta, const void* h_y, phi_dr* out);
+/* M' (reduced rows) and W (their window edge). */
+phi_status phi_dr_size(phi_dr dr, int64_t* n_red, int32_t* w);
+/* Copy the reduced block: bases [M'][2], window sizes [M'] (= W), windows
+ * complex128 [M'][W*W], y' complex128 [M'], Lam [M'], cell [M'].  Any output
+ * pointer may be NULL. */
+phi_status phi_dr_copy(phi_dr dr, int32_t* h_base, uint8_t* h_stencil, void* h_windows, void* h_y, double* h_lam,
+                       int64_t* h_cell);
+phi_status phi_dr_destroy(phi_dr dr);
+
 const char* phi_status_string(phi_status s);
 
 #ifdef __cplusplus

@@ -25,7 +25,7 @@ EXPORTS = [
     "phi_plan_load_g", "phi_plan_set_theta", "phi_plan_get_info", "phi_plan_set_flags", "phi_plan_set_tuning", "phi_to_plan_order",
     "phi_from_plan_order", "phi_forward", "phi_adjoint", "l2ball_dual_step",
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
-    "phi_status_string",
+    "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
 ]
 
 
@@ -99,6 +99,10 @@ def load():
         "phi_plan_get_timing": [P, I32, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_char_p),
                                 ctypes.POINTER(I32), ctypes.POINTER(I64)],
         "phi_plan_autotune": [P, V, I32],
+        "phi_dr_create": [I32, I32, I64, V, V, V, I32, D, V, ctypes.POINTER(P)],
+        "phi_dr_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
+        "phi_dr_copy": [P, V, V, V, V, V, V],
+        "phi_dr_destroy": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -7,7 +7,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphi.so")
-SOURCES = [os.path.join(CSRC, "phi_kernels.hip"), os.path.join(CSRC, "phi_host.cpp")]
+SOURCES = [os.path.join(CSRC, "phi_kernels.hip"), os.path.join(CSRC, "phi_host.cpp"),
+           os.path.join(CSRC, "phi_dr.cpp")]
 ARCH = os.environ.get("PHI_OFFLOAD_ARCH", "gfx950")
 
 

@@ -202,3 +202,36 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def dr_reduce(ky, kx, base, stencil, windows, theta=1.0, y=None):
+    """Gridding reduction of one block (libphi, host FP64): returns a dict with
+    the reduced rows' bases [M', 2], window sizes [M'], windows (complex128,
+    W*W each), y' [M'], Lam [M'] and cell indices [M'] (sorted)."""
+    lib = L.load()
+    base = np.ascontiguousarray(base, dtype=np.int32).reshape(-1, 2)
+    stencil = np.ascontiguousarray(stencil, dtype=np.uint8)
+    w = np.ascontiguousarray(windows)
+    if w.dtype == np.complex128:
+        kind = L.HOST_C128
+    elif w.dtype == np.complex64:
+        kind = L.HOST_C64
+    else:
+        raise TypeError("windows must be complex128 or complex64")
+    yy = None if y is None else np.ascontiguousarray(y, dtype=np.complex128)
+    h = ctypes.c_void_p()
+    L.check(lib.phi_dr_create(int(ky), int(kx), len(stencil), _ptr(base), _ptr(stencil), _ptr(w), kind,
+                              float(theta), _ptr(yy), ctypes.byref(h)), "phi_dr_create")
+    try:
+        n = ctypes.c_int64()
+        W = ctypes.c_int32()
+        L.check(lib.phi_dr_size(h, ctypes.byref(n), ctypes.byref(W)), "phi_dr_size")
+        m, W = n.value, W.value
+        out = dict(base=np.empty((m, 2), np.int32), S=np.empty(m, np.uint8),
+                   windows=np.empty(m * W * W, np.complex128), y=np.empty(m, np.complex128),
+                   lam=np.empty(m, np.float64), cell=np.empty(m, np.int64), W=W)
+        L.check(lib.phi_dr_copy(h, _ptr(out["base"]), _ptr(out["S"]), _ptr(out["windows"]), _ptr(out["y"]),
+                                _ptr(out["lam"]), _ptr(out["cell"])), "phi_dr_copy")
+    finally:
+        lib.phi_dr_destroy(h)
+    return out
