@@ -56,9 +56,14 @@ def traffic_for(kernel, launch_alg_bytes):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def generate(name, log_every=8):
+def generate(name, log_every=8, channels=0):
     import synth
     prob = synth.make_problem(name)
+    if channels and channels < prob.L:
+        sel = np.linspace(0, prob.L - 1, channels).round().astype(int)
+        prob = synth.make_problem(name, L=channels, n_blocks=[prob.n_blocks[l] for l in sel],
+                                  n_vis=[prob.n_vis[l] for l in sel],
+                                  nu=None if prob.nu is None else prob.nu[sel])
     t0 = time.time()
     blocks = []
     for k, (l, b) in enumerate(prob.block_list()):
@@ -125,6 +130,62 @@ def cpu_baseline(prob, plan, theta, budget_s=30.0):
     return base, err
 
 
+def run_dr(args, prob, blocks, theta, y_user, starts, s_y, s_x, results, dev):
+    """Reduce every block (host, FP64) and time the reduced dual step with the
+    same precision and launch form as the headline; returns a summary."""
+    import torch
+    from paper_2209_07604_amd import Plan, dr_reduce, GRAPH, PERSISTENT
+    t0 = time.time()
+    outs = []
+    for k, (b_, S_, w_) in enumerate(blocks):
+        outs.append(dr_reduce(prob.Ky, prob.Kx, b_, S_, w_, theta[k],
+                              y_user[starts[k]:starts[k + 1]].astype(np.complex128)))
+    t_red = time.time() - t0
+    n_red = [len(o["S"]) for o in outs]
+    log("[bench] reduction %.1f s, M' per block %s" % (t_red, n_red))
+    prec = "f16"
+    p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_red, np.concatenate([o["base"] for o in outs]),
+             np.concatenate([o["S"] for o in outs]), s_y, s_x, None, g_prec=prec, device=dev)
+    for k, o in enumerate(outs):
+        p.load_g(k, o["windows"].astype(np.complex64))
+    yr = p.to_plan(torch.from_numpy(np.concatenate([o["y"] for o in outs]).astype(np.complex64)).to(dev))
+    del outs
+    p.autotune(3)
+    p.set_flags(GRAPH | (PERSISTENT if p.info()["persist_blocks"] else 0))
+    mr = int(sum(n_red))
+    eps = torch.tensor([np.sqrt(m + 2.0 * np.sqrt(m)) for m in n_red], dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    v = (0.1 * torch.complex(torch.randn(mr, generator=gen, device=dev),
+                             torch.randn(mr, generator=gen, device=dev))).contiguous()
+    xt = torch.from_numpy(np.stack([0.5 * prob.image(l) for l in range(prob.L)])).to(dev)
+    grad = torch.empty_like(xt)
+    rho = torch.empty(len(n_red), dtype=torch.float64, device=dev)
+    res = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        p.dual_step(xt, v, yr, eps, None, grad, rho, res)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        p.dual_step(xt, v, yr, eps, None, grad, rho, res)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    info = p.info()
+    M = int(sum(len(s) for (_, s, _) in blocks))
+    ref = results.get("batched_f16")
+    out = {"M": M, "M_reduced": mr, "M_over_M_reduced": M / mr, "taps_G": ref["info"]["n_taps"] if ref else None,
+           "taps_H": info["n_taps"], "g_bytes_f16": ref["info"]["g_bytes"] if ref else None,
+           "h_bytes_f16": info["g_bytes"], "reduce_host_s": t_red, "ms_per_step_reduced": ms,
+           "ms_per_step_unreduced": ref["ms_per_step"] if ref else None,
+           "visibilities_per_s_reduced": M / (ms * 1e-3), "tile": info["tile"]}
+    if ref:
+        out["speedup"] = ref["ms_per_step"] / ms
+    log("[bench] reduced step: %s" % out)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +197,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile edge (skips the autotuner)")
     ap.add_argument("--persist", type=int, default=0, help="persistent G-stage grid with --tile")
+    ap.add_argument("--channels", type=int, default=0, help="use this many channels of the configuration")
+    ap.add_argument("--dr", action="store_true",
+                    help="also time the visibility-gridding reduced step (Section 3.4) on the same data")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -149,7 +213,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    prob, blocks = generate(args.config)
+    prob, blocks = generate(args.config, channels=args.channels)
     L = prob.L
     n_vis = [len(s) for (_, s, _) in blocks]
     base = np.concatenate([b for (b, _, _) in blocks])
@@ -166,7 +230,8 @@ def main():
             p.load_g(k, w)
         plans[prec] = p
         log("[bench] plan %s ready (%.0f s), info %s" % (prec, time.time() - t0, p.info()))
-    del blocks
+    if not args.dr:
+        del blocks
 
     # inputs: x~ = x/2, y = theta Phi0 x + n at 30 dB (theta from the c64 form), v ~ 0.1 CN
     gen = torch.Generator(device=dev)
@@ -254,6 +319,9 @@ def main():
         log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
             form, ms, M / (ms * 1e-3), {k_: round(v_ / max(calls, 1), 3) for k_, v_ in stages.items()}))
 
+    if args.dr:
+        line_dr = run_dr(args, prob, blocks, theta, (th_vis * pref.from_plan(y0) + noise).cpu().numpy(),
+                         starts, s_y, s_x, results, dev)
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -299,6 +367,8 @@ def main():
     }
     if "plain_c64" in results:
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
+    if args.dr:
+        line["dimensionality_reduction"] = line_dr
     if not args.no_cpu_baseline:
         hp = plans[head.split("_")[1]]
         hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0))
