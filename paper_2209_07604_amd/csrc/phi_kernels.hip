@@ -42,19 +42,6 @@ __device__ __forceinline__ float dppf(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 
-// Sum over the 64 lanes of a wave in a fixed order; every lane gets the sum.
-__device__ __forceinline__ float wave_sum(float v) {
-  v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]: pairs
-  v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]: quads
-  v += dppf<0x141>(v);  // row_half_mirror: 8-lane halves
-  v += dppf<0x140>(v);  // row_mirror: 16-lane rows
-  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
-  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
-  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
-  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
-  return (r0 + r1) + (r2 + r3);
-}
-
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -329,62 +316,153 @@ template <>
 struct GRaw<0> {
   using T = float2;
 };
+// (gx, gy) of a raw tap.  The FP16 halves stay 16-bit so that the multiply
+// below can take them straight into a mixed-precision FMA.
 template <int GP>
-__device__ __forceinline__ float2 unpack_g(typename GRaw<GP>::T r);
-template <>
-__device__ __forceinline__ float2 unpack_g<0>(float2 r) {
-  return r;
-}
-template <>
-__device__ __forceinline__ float2 unpack_g<1>(uint32_t r) {
-  __half2 h;
-  __builtin_memcpy(&h, &r, 4);
-  return __half22float2(h);
-}
-template <>
-__device__ __forceinline__ float2 unpack_g<2>(uint32_t r) {
-  return make_float2(__uint_as_float(r << 16), __uint_as_float(r & 0xFFFF0000u));
+__device__ __forceinline__ float g_re(typename GRaw<GP>::T r) {
+  if constexpr (GP == 0) {
+    return r.x;
+  } else if constexpr (GP == 1) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(r & 0xFFFFu));
+  } else {
+    return __uint_as_float(r << 16);
+  }
 }
 template <int GP>
-__device__ __forceinline__ typename GRaw<GP>::T zero_g() {
-  if constexpr (GP == 0)
-    return make_float2(0.f, 0.f);
-  else
-    return 0u;
+__device__ __forceinline__ float g_im(typename GRaw<GP>::T r) {
+  if constexpr (GP == 0) {
+    return r.y;
+  } else if constexpr (GP == 1) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(r >> 16));
+  } else {
+    return __uint_as_float(r & 0xFFFF0000u);
+  }
 }
 
-__device__ __forceinline__ uint32_t meta_at(uint32_t mcur, uint32_t mnxt, int off) {
-  return (uint32_t)(off < 64 ? __builtin_amdgcn_readlane((int)mcur, off)
-                             : __builtin_amdgcn_readlane((int)mnxt, off - 64));
+// Lane sums for the gather, in a fixed order.  v_permlane32_swap folds the
+// 32-lane halves of two vectors into one (lanes 0-31 carry the first vector's
+// half sums, 32-63 the second's); v_permlane16_swap folds 16-lane rows the
+// same way; the DPP steps then sum inside each 16-lane row.
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
+__device__ __forceinline__ float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dppf<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dppf<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dppf<0x141>(v);  // row_half_mirror
+  v += dppf<0x140>(v);  // row_mirror
+  return v;
+}
+// Sums over 64 lanes of (a0, a1) for one window: returns (sum a0, sum a1).
+__device__ __forceinline__ float2 lane_sum1(float a0, float a1) {
+  const float h = fold32(a0, a1);           // [a0 | a1] in 32-lane halves
+  const float q = row_sum16(fold16(h, h));  // rows: a0, a0, a1, a1
+  return make_float2(readlane_f(q, 0), readlane_f(q, 32));
+}
+// Two windows p and q: (sum p0, sum p1, sum q0, sum q1).
+__device__ __forceinline__ float4 lane_sum2(float p0, float p1, float q0, float q1) {
+  const float q = row_sum16(fold16(fold32(p0, p1), fold32(q0, q1)));  // rows: p0, q0, p1, q1
+  return make_float4(readlane_f(q, 0), readlane_f(q, 32), readlane_f(q, 16), readlane_f(q, 48));
+}
+
+// One wave streams the G taps of consecutive windows of a work item.  Lanes
+// span the S*S taps of a window (row-major) in NK steps of 64 (NK = steps of
+// the item's largest window); lanes past a smaller window re-read its last
+// tap, so every fetch issues exactly NK loads.  Each fetch address is the
+// window's first tap (uniform) plus a per-lane 32-bit byte offset kept for
+// runs of equal S.  The window's metadata word comes from two 64-visibility
+// chunks held one per lane (the fetch runs up to D windows ahead).
+template <int GP, int NK>
+struct GStream {
+  using R = typename GRaw<GP>::T;
+  static constexpr uint32_t kEb = sizeof(R);
+  const char* __restrict__ G;
+  int64_t tap;      // next window's first tap
+  int64_t tap_end;  // re-read target once the range is exhausted
+  int j, v1, S = -1;
+  uint32_t fto[NK];
+  __device__ __forceinline__ void fetch(R (&g)[NK], uint32_t& m, uint32_t mcur, uint32_t mnxt, int cb, int lane) {
+    const bool live = j < v1;
+    const int rel = j - cb;  // < 64 + D
+    const uint32_t ma = (uint32_t)__builtin_amdgcn_readlane((int)mcur, rel & 63);
+    const uint32_t mb = (uint32_t)__builtin_amdgcn_readlane((int)mnxt, rel & 63);
+    const uint32_t mt = live ? (rel < 64 ? ma : mb) : 0u;
+    m = mt;
+    const int s = 2 * (int)(mt >> 26) + 1;
+    if (s != S) {
+      S = s;
+#pragma unroll
+      for (int k = 0; k < NK; ++k) fto[k] = (uint32_t)min(k * 64 + lane, s * s - 1) * kEb;
+    }
+    const char* gp = G + (live ? tap : tap_end) * (int64_t)kEb;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) g[k] = *reinterpret_cast<const R*>(gp + fto[k]);
+    tap += live ? s * s : 0;
+    ++j;
+  }
+};
+
+// Per-S lane layout of a window inside a pitch-P LDS tile: the byte offset of
+// each step's cell from the window origin.  Lanes past the window hold a
+// large offset, and the address min(base + off, park) sends them to the fixed
+// cell `park` (a zero cell for the gather, a private spare cell for the
+// scatter), so no step needs a mask or a divergent branch.
+template <int NK>
+struct TapLayout {
+  int S = -1;
+  uint32_t off[NK];  // bytes; 0x40000000 past the window
+  __device__ __forceinline__ void set(int s, int P, int lane) {
+    S = s;
+    const int S2 = s * s;
+    const float rS = __builtin_amdgcn_rcpf((float)s);
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const int t = k * 64 + lane;
+      const uint32_t cell = (uint32_t)(t + tap_row(min(t, S2 - 1), rS) * (P - s));  // row * P + column
+      off[k] = t < S2 ? cell * 8u : 0x40000000u;
+    }
+  }
+  __device__ __forceinline__ uint32_t addr(uint32_t base_b, int k, uint32_t park) const {
+    return min(base_b + off[k], park);
+  }
+};
 
 // One wave per work item (a run of plan-order visibilities of one block whose
-// window origins lie in one T x T uv tile).  Lanes span the S*S taps of one
-// window (row-major); the per-visibility sum is a fixed-order wave reduction.
+// window origins lie in one T x T uv tile).  The per-visibility sum over the
+// window's taps is a fixed-order lane reduction, taken for two windows at a
+// time.
 //
 // Latency hiding: the G taps of the next D windows are loaded into registers
-// while the current window is reduced.  Each fetch issues exactly NK loads
-// (NK = 64-tap steps of the item's largest window; lanes past a smaller
-// window re-read a valid tap), and the steady-state loop has no guarded
-// fetch, so the wait before a window is used always leaves the later D - 1
-// fetches in flight.  Per-chunk vectors (metadata, v, y) are loaded one
-// 64-visibility chunk ahead of their use.  NK is a template parameter picked
-// per item at run time (1..7 for S <= 21), D = about 12 / NK.
+// while the current windows are reduced.  Each fetch issues exactly NK loads
+// and the steady-state loop has no guarded fetch, so the wait before a window
+// is used always leaves the later fetches in flight.  NK is a template
+// parameter picked per item at run time (1..7 for S <= 21).
 //
 // Gather: the item's grid region (its tile plus the window halo, wrapped
 // periodically) is first copied into LDS, so each window reads its S*S cells
 // from LDS and only G streams through the vector memory path.  Lane i of
 // each chunk keeps visibility i's result: the residual, its FP64 norms and
 // the stores are lane-parallel and coalesced.
-// windows prefetched per wave for windows of NK 64-tap steps (about 24
-// registers of G taps in flight for 32-bit taps, half as deep for complex64)
-#ifndef PHI_DEPTH_REGS
-#define PHI_DEPTH_REGS 16
+//
+// Prefetch depth: about PHI_GATHER_DEPTH_REGS (gather) or
+// PHI_SCATTER_DEPTH_REGS (scatter) registers of 32-bit taps in flight per
+// wave (half as many windows for complex64); deeper prefetch costs
+// occupancy.
+#ifndef PHI_GATHER_DEPTH_REGS
+#define PHI_GATHER_DEPTH_REGS 8
 #endif
-template <int GP, int NK>
+#ifndef PHI_SCATTER_DEPTH_REGS
+#define PHI_SCATTER_DEPTH_REGS 16
+#endif
+template <int GP, int NK, int REGS>
 struct Depth {
-  static constexpr int regs = GP == 0 ? PHI_DEPTH_REGS / 2 : PHI_DEPTH_REGS;
-  static constexpr int value = regs / NK < 2 ? 2 : regs / NK;
+  static constexpr int regs = GP == 0 ? REGS / 2 : REGS;
+  static constexpr int value = (regs / NK) < 2 ? 2 : regs / NK;
 };
 
 template <int GP, int MODE, int NK, int D>
@@ -392,123 +470,136 @@ __device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, in
                                             float2* __restrict__ vis, const float2* __restrict__ yv,
                                             double& rho2, double& res2, const float2* __restrict__ tile) {
   using R = typename GRaw<GP>::T;
-  const R* __restrict__ G = static_cast<const R*>(a.G);
   const int lane = threadIdx.x & 63;
   const int vlast = v1 - 1, P = item.pitch;
   const float th = a.theta[item.blk];
   float inv_sig = 1.f;
   if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+  // 64-visibility chunks held one value per lane: metadata of chunks cb and
+  // cb + 64 (read per window) with cb + 128 in flight; v and y of chunk cb
+  // (read at its flush) with cb + 64 in flight.  Per-window code only reads
+  // registers that were filled by moves at a chunk boundary, so no wait for a
+  // chunk load falls between a window's G fetch and its use (such a wait
+  // would drain the whole prefetch).
   int cb = v0;
   uint32_t mcur = a.meta[min(cb + lane, vlast)];
   uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
-  float2 vc = make_float2(0.f, 0.f), yc = vc;
+  uint32_t mstg = a.meta[min(cb + 128 + lane, vlast)];
+  float2 vc = make_float2(0.f, 0.f), yc = vc, vstg = vc, ystg = vc;
   if (MODE == 1) {
     vc = vis[min(cb + lane, vlast)];
     yc = yv[min(cb + lane, vlast)];
+    vstg = vis[min(cb + 64 + lane, vlast)];
+    ystg = yv[min(cb + 64 + lane, vlast)];
   }
   R gb[D][NK];
   uint32_t ms[D];
-  int64_t tapf = tap0;
-  int jf = v0;
-  // per-lane tap index clamped to the window, kept for runs of equal S
-  int fS = -1;
-  int ft[NK];
-  auto fetch = [&](R(&g)[NK], uint32_t& m) {
-    const bool live = jf < v1;
-    const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
-    m = mt;
-    const int S = 2 * (int)(mt >> 26) + 1;
-    if (S != fS) {
-      fS = S;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) ft[k] = min(k * 64 + lane, S * S - 1);
-    }
-    const R* __restrict__ gp = G + (live ? tapf : tap0);
-#pragma unroll
-    for (int k = 0; k < NK; ++k) g[k] = gp[ft[k]];
-    tapf += live ? S * S : 0;
-    ++jf;
-  };
-  float2 res = make_float2(0.f, 0.f);
-  // per-lane LDS offset (row * P + column) of each tap step, kept for runs of
-  // equal S; lanes past the window read a valid cell and add zero
-  int pS = -1;
-  int off[NK];
-  uint32_t live_mask = 0;
+  GStream<GP, NK> gs{static_cast<const char*>(a.G), tap0, tap0, v0, v1};
+  TapLayout<NK> lay;
+  float2 res = make_float2(0.f, 0.f);  // lane i: sum for visibility cb + i (theta applied at flush)
   auto flush = [&]() {
     if (cb + lane < v1) {
+      const float px = th * res.x, py = th * res.y;
       if (MODE == 0) {
-        vis[cb + lane] = res;
+        vis[cb + lane] = make_float2(px, py);
       } else {
-        const float2 c = make_float2(vc.x * inv_sig + res.x - yc.x, vc.y * inv_sig + res.y - yc.y);
+        const float2 c = make_float2(vc.x * inv_sig + px - yc.x, vc.y * inv_sig + py - yc.y);
         vis[cb + lane] = c;
-        const double rx = (double)res.x - (double)yc.x, ry = (double)res.y - (double)yc.y;
+        const double rx = (double)px - (double)yc.x, ry = (double)py - (double)yc.y;
         rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
         res2 += rx * rx + ry * ry;
       }
     }
   };
-  auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
+  auto advance = [&](int i) {
     if (i == cb + 64) {
       flush();
       cb += 64;
       mcur = mnxt;
-      mnxt = a.meta[min(cb + 64 + lane, vlast)];
+      mnxt = mstg;
+      mstg = a.meta[min(cb + 128 + lane, vlast)];
       if (MODE == 1) {
-        vc = vis[min(cb + lane, vlast)];
-        yc = yv[min(cb + lane, vlast)];
+        vc = vstg;
+        yc = ystg;
+        vstg = vis[min(cb + 64 + lane, vlast)];
+        ystg = yv[min(cb + 64 + lane, vlast)];
       }
       res = make_float2(0.f, 0.f);
     }
+  };
+  // this lane's partial (sum over its taps of g * X) for one window; lanes
+  // past the window read the zero cell behind the tile
+  const uint32_t park = (uint32_t)(P * P) * 8u;
+  auto partial = [&](const R(&g)[NK], uint32_t mt, float& ax, float& ay) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
-    if (S != pS) {
-      pS = S;
-      const float rS = __builtin_amdgcn_rcpf((float)S);
-      live_mask = 0;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        const int t0 = k * 64 + lane;
-        const int t = min(t0, S2 - 1);
-        const int ii = tap_row(t, rS);
-        off[k] = ii * P + (t - ii * S);
-        live_mask |= (t0 < S2 ? 1u : 0u) << k;
-      }
-    }
-    const int base = (by - item.ty0) * P + (bx - item.tx0);
-    float ax = 0.f, ay = 0.f;
+    if (S != lay.S) lay.set(S, P, lane);
+    const uint32_t base_b = (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+    ax = 0.f;
+    ay = 0.f;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       if (k * 64 < S2) {
-        float2 gg = unpack_g<GP>(g[k]);
-        if (!(live_mask & (1u << k))) gg = make_float2(0.f, 0.f);
-        const float2 X = tile[base + off[k]];
-        ax += gg.x * X.x - gg.y * X.y;
-        ay += gg.x * X.y + gg.y * X.x;
+        const float2 X =
+            *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tile) + lay.addr(base_b, k, park));
+        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+        ax = __builtin_fmaf(gx, X.x, ax);
+        ax = __builtin_fmaf(-gy, X.y, ax);
+        ay = __builtin_fmaf(gx, X.y, ay);
+        ay = __builtin_fmaf(gy, X.x, ay);
       }
     }
-    const float px = wave_sum(ax) * th, py = wave_sum(ay) * th;
-    if (lane == i - cb) res = make_float2(px, py);
+  };
+  auto place = [&](int i, float px, float py) {
+    const bool me = lane == i - cb;
+    res.x = me ? px : res.x;
+    res.y = me ? py : res.y;
   };
 #pragma unroll
-  for (int d = 0; d < D; ++d) fetch(gb[d], ms[d]);
+  for (int d = 0; d < D; ++d) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+  auto single = [&](int d, int i) {
+    advance(i);
+    float ax, ay;
+    partial(gb[d], ms[d], ax, ay);
+    gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+    const float2 s = lane_sum1(ax, ay);
+    place(i, s.x, s.y);
+  };
   int i = v0;
   for (; i + D <= v1; i += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      step(gb[d], ms[d], i + d);
-      fetch(gb[d], ms[d]);
+    for (int d = 0; d + 1 < D; d += 2) {
+      advance(i + d);
+      float ax0, ay0, ax1, ay1;
+      partial(gb[d], ms[d], ax0, ay0);
+      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      partial(gb[d + 1], ms[d + 1], ax1, ay1);
+      gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
+      const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
+      place(i + d, s.x, s.y);
+      advance(i + d + 1);  // the pair may straddle a chunk boundary
+      place(i + d + 1, s.z, s.w);
     }
+    if constexpr (D & 1) single(D - 1, i + D - 1);
   }
 #pragma unroll
-  for (int d = 0; d < D - 1; ++d)
-    if (i + d < v1) step(gb[d], ms[d], i + d);
+  for (int d = 0; d < D - 1; ++d) {
+    if (i + d < v1) {
+      advance(i + d);
+      float ax, ay;
+      partial(gb[d], ms[d], ax, ay);
+      const float2 s = lane_sum1(ax, ay);
+      place(i + d, s.x, s.y);
+    }
+  }
   if (cb < v1) flush();
 }
 
 // kGatherWaves waves per work-group share one LDS copy of the item's grid
-// region; wave w takes the w-th quarter of the item's visibilities.
-template <int GP, int MODE>
+// region; wave w takes the w-th quarter of the item's visibilities.  NKM is
+// the largest step count instantiated (from the plan's largest window), so a
+// plan of small windows does not pay the registers of the 21 x 21 path.
+template <int GP, int MODE, int NKM>
 __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* __restrict__ vis,
                                                               const float2* __restrict__ yv,
                                                               double* __restrict__ item_norms, int it0, int it1) {
@@ -528,6 +619,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
       gc -= (gc >= a.Kx) ? a.Kx : 0;
       tile[e] = grid[(size_t)gr * a.Kx + gc];
     }
+    if (tid == 0) tile[P * P] = make_float2(0.f, 0.f);  // the zero cell
     __syncthreads();
     const int n = item.v1 - item.v0, q = (n + kGatherWaves - 1) / kGatherWaves;
     const int wv0 = min(item.v0 + w * q, item.v1), wv1 = min(item.v0 + (w + 1) * q, item.v1);
@@ -538,9 +630,11 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
     double rho2 = 0.0, res2 = 0.0;
     if (wv0 < wv1) {
       switch (nk) {
-#define PHI_G_CASE(K)                                                                                       \
-  case K:                                                                                                   \
-    gather_item<GP, MODE, K, Depth<GP, K>::value>(a, item, wv0, wv1, wtap, vis, yv, rho2, res2, tile); \
+#define PHI_G_CASE(K)                                                                                      \
+  case K:                                                                                                  \
+    if constexpr (K <= NKM)                                                                                \
+      gather_item<GP, MODE, K, Depth<GP, K, PHI_GATHER_DEPTH_REGS>::value>(a, item, wv0, wv1, wtap, vis, \
+                                                                           yv, rho2, res2, tile);      \
     break;
         PHI_G_CASE(1)
         PHI_G_CASE(2)
@@ -548,10 +642,10 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
         PHI_G_CASE(4)
         PHI_G_CASE(5)
         PHI_G_CASE(6)
-        default:
-          gather_item<GP, MODE, 7, Depth<GP, 7>::value>(a, item, wv0, wv1, wtap, vis, yv, rho2, res2, tile);
-          break;
+        PHI_G_CASE(7)
 #undef PHI_G_CASE
+        default:
+          break;
       }
     }
     if (MODE == 1) {
@@ -581,14 +675,16 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
 // window halo) and adds conj(g) theta v for its visibilities in plan order.
 // The taps of one window are distinct cells, so each read-add-write step has
 // no two lanes on one address; no atomics are needed and the order is fixed.
-// The G taps are prefetched exactly as in the gather.
+// Lanes past the window add into 64 spare cells behind the accumulator (one
+// per lane), so no step needs a divergent branch.  The G taps are prefetched
+// exactly as in the gather.
 template <int GP, int MODE, int NK, int D>
 __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, float2* __restrict__ vis,
                                              float2* __restrict__ acc) {
   using R = typename GRaw<GP>::T;
-  const R* __restrict__ G = static_cast<const R*>(a.G);
   const int lane = threadIdx.x;
   const int v0 = item.v0, v1 = item.v1, vlast = v1 - 1, P = item.pitch;
+  const uint32_t park = (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
   const float th = a.theta[item.blk];
   float sc = 1.f;
   if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
@@ -600,85 +696,59 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
     }
     return make_float2(th * v.x, th * v.y);
   };
+  // chunks as in the gather: metadata of chunks cb, cb + 64 and (in flight)
+  // cb + 128; theta v of chunk cb (read per window) and raw v of cb + 64
   int cb = v0;
   uint32_t mcur = a.meta[min(cb + lane, vlast)];
   uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
+  uint32_t mstg = a.meta[min(cb + 128 + lane, vlast)];
   float2 avc = take_av(vis[min(cb + lane, vlast)], cb);
   float2 vraw = vis[min(cb + 64 + lane, vlast)];
   R gb[D][NK];
   uint32_t ms[D];
-  int64_t tapf = item.tap0;
-  int jf = v0;
-  int fS = -1;
-  int ft[NK];
-  auto fetch = [&](R(&g)[NK], uint32_t& m) {
-    const bool live = jf < v1;
-    const uint32_t mt = live ? meta_at(mcur, mnxt, jf - cb) : 0u;
-    m = mt;
-    const int S = 2 * (int)(mt >> 26) + 1;
-    if (S != fS) {
-      fS = S;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) ft[k] = min(k * 64 + lane, S * S - 1);
-    }
-    const R* __restrict__ gp = G + (live ? tapf : item.tap0);
-#pragma unroll
-    for (int k = 0; k < NK; ++k) g[k] = gp[ft[k]];
-    tapf += live ? S * S : 0;
-    ++jf;
-  };
-  int pS = -1;
-  int off[NK];
-  uint32_t live_mask = 0;
+  GStream<GP, NK> gs{static_cast<const char*>(a.G), item.tap0, item.tap0, v0, v1};
+  TapLayout<NK> lay;
   auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
     if (i == cb + 64) {
       cb += 64;
       mcur = mnxt;
-      mnxt = a.meta[min(cb + 64 + lane, vlast)];
+      mnxt = mstg;
+      mstg = a.meta[min(cb + 128 + lane, vlast)];
       avc = take_av(vraw, cb);
       vraw = vis[min(cb + 64 + lane, vlast)];
     }
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
-    if (S != pS) {
-      pS = S;
-      const float rS = __builtin_amdgcn_rcpf((float)S);
-      live_mask = 0;
-#pragma unroll
-      for (int k = 0; k < NK; ++k) {
-        const int t0 = k * 64 + lane;
-        const int t = min(t0, S2 - 1);
-        const int ii = tap_row(t, rS);
-        off[k] = ii * P + (t - ii * S);
-        live_mask |= (t0 < S2 ? 1u : 0u) << k;
-      }
-    }
+    if (S != lay.S) lay.set(S, P, lane);
     const float vx = readlane_f(avc.x, i - cb), vy = readlane_f(avc.y, i - cb);
-    const int base = (by - item.ty0) * P + (bx - item.tx0);
+    const uint32_t base_b = (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+    char* accb = reinterpret_cast<char*>(acc);
     // all steps of one window touch distinct cells: read them all, then add
     // and write, so the window costs one LDS round trip, not one per step
     float2 cur[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k)
-      if (k * 64 < S2 && (live_mask & (1u << k))) cur[k] = acc[base + off[k]];
+      if (k * 64 < S2) cur[k] = *reinterpret_cast<float2*>(accb + lay.addr(base_b, k, park));
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      if (k * 64 < S2 && (live_mask & (1u << k))) {
-        const float2 gg = unpack_g<GP>(g[k]);
-        cur[k].x += gg.x * vx + gg.y * vy;
-        cur[k].y += gg.x * vy - gg.y * vx;
-        acc[base + off[k]] = cur[k];
+      if (k * 64 < S2) {
+        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+        cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
+        cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
+        cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
+        cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
+        *reinterpret_cast<float2*>(accb + lay.addr(base_b, k, park)) = cur[k];
       }
     }
   };
 #pragma unroll
-  for (int d = 0; d < D; ++d) fetch(gb[d], ms[d]);
+  for (int d = 0; d < D; ++d) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
   int i = v0;
   for (; i + D <= v1; i += D) {
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       step(gb[d], ms[d], i + d);
-      fetch(gb[d], ms[d]);
+      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
     }
   }
 #pragma unroll
@@ -686,10 +756,10 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
     if (i + d < v1) step(gb[d], ms[d], i + d);
 }
 
-template <int GP, int MODE>
+template <int GP, int MODE, int NKM>
 __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vis, float2* __restrict__ partials,
                                                 int it0, int it1) {
-  extern __shared__ float2 acc[];
+  extern __shared__ float2 acc[];  // pitch^2 cells, then 64 spare cells
   const int lane = threadIdx.x;
   for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
     const Item item = a.items[it];
@@ -699,13 +769,21 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
     const int smax = P - a.T + 1;
     const int nk = (smax * smax + 63) / 64;
     switch (nk) {
-      case 1: scatter_item<GP, MODE, 1, Depth<GP, 1>::value>(a, item, vis, acc); break;
-      case 2: scatter_item<GP, MODE, 2, Depth<GP, 2>::value>(a, item, vis, acc); break;
-      case 3: scatter_item<GP, MODE, 3, Depth<GP, 3>::value>(a, item, vis, acc); break;
-      case 4: scatter_item<GP, MODE, 4, Depth<GP, 4>::value>(a, item, vis, acc); break;
-      case 5: scatter_item<GP, MODE, 5, Depth<GP, 5>::value>(a, item, vis, acc); break;
-      case 6: scatter_item<GP, MODE, 6, Depth<GP, 6>::value>(a, item, vis, acc); break;
-      default: scatter_item<GP, MODE, 7, Depth<GP, 7>::value>(a, item, vis, acc); break;
+#define PHI_S_CASE(K)                                                                                     \
+  case K:                                                                                                 \
+    if constexpr (K <= NKM)                                                                               \
+      scatter_item<GP, MODE, K, Depth<GP, K, PHI_SCATTER_DEPTH_REGS>::value>(a, item, vis, acc);      \
+    break;
+      PHI_S_CASE(1)
+      PHI_S_CASE(2)
+      PHI_S_CASE(3)
+      PHI_S_CASE(4)
+      PHI_S_CASE(5)
+      PHI_S_CASE(6)
+      PHI_S_CASE(7)
+#undef PHI_S_CASE
+      default:
+        break;
     }
     __syncthreads();
     float2* out = partials + item.poff;
@@ -940,14 +1018,30 @@ hipError_t launch_colfft_inv(int Ky, const float2* grid, float2* half, const flo
   }
 }
 
-template <int GP>
-static hipError_t gather_gp(int mode, const GArgs& a, float2* vis, const float2* y, double* norms, size_t lds,
-                            int it0, int it1, int nb, hipStream_t s) {
-  if (mode == 0)
-    hipLaunchKernelGGL((k_gather<GP, 0>), dim3(nb), dim3(64 * kGatherWaves), lds, s, a, vis, y, norms, it0, it1);
+// Step-count class of a plan: the kernels instantiate item paths up to NKM
+// 64-tap steps (windows up to 7 x 7, 17 x 17 or 21 x 21).
+static int nk_class(int max_pitch, int T) {
+  const int smax = max_pitch - T + 1, nk = (smax * smax + 63) / 64;
+  return nk <= 1 ? 1 : nk <= 5 ? 5 : 7;
+}
+
+template <int GP, int MODE>
+static hipError_t gather_m(int nkc, const GArgs& a, float2* vis, const float2* y, double* norms, size_t lds,
+                           int it0, int it1, int nb, hipStream_t s) {
+  const dim3 g(nb), b(64 * kGatherWaves);
+  if (nkc == 1)
+    hipLaunchKernelGGL((k_gather<GP, MODE, 1>), g, b, lds, s, a, vis, y, norms, it0, it1);
+  else if (nkc == 5)
+    hipLaunchKernelGGL((k_gather<GP, MODE, 5>), g, b, lds, s, a, vis, y, norms, it0, it1);
   else
-    hipLaunchKernelGGL((k_gather<GP, 1>), dim3(nb), dim3(64 * kGatherWaves), lds, s, a, vis, y, norms, it0, it1);
+    hipLaunchKernelGGL((k_gather<GP, MODE, 7>), g, b, lds, s, a, vis, y, norms, it0, it1);
   return hipGetLastError();
+}
+template <int GP>
+static hipError_t gather_gp(int mode, int nkc, const GArgs& a, float2* vis, const float2* y, double* norms,
+                            size_t lds, int it0, int it1, int nb, hipStream_t s) {
+  return mode == 0 ? gather_m<GP, 0>(nkc, a, vis, y, norms, lds, it0, it1, nb, s)
+                   : gather_m<GP, 1>(nkc, a, vis, y, norms, lds, it0, it1, nb, s);
 }
 
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y, double* item_norms,
@@ -955,24 +1049,34 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
   const int n = it1 - it0;
   if (n <= 0) return hipSuccess;
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
-  const size_t lds = (size_t)max_pitch * max_pitch * sizeof(float2);
+  const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell
   if (lds > 65536) return hipErrorInvalidValue;
+  const int nkc = nk_class(max_pitch, a.T);
   switch (gprec) {
-    case 0: return gather_gp<0>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
-    case 1: return gather_gp<1>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
-    case 2: return gather_gp<2>(mode, a, vis, y, item_norms, lds, it0, it1, nb, s);
+    case 0: return gather_gp<0>(mode, nkc, a, vis, y, item_norms, lds, it0, it1, nb, s);
+    case 1: return gather_gp<1>(mode, nkc, a, vis, y, item_norms, lds, it0, it1, nb, s);
+    case 2: return gather_gp<2>(mode, nkc, a, vis, y, item_norms, lds, it0, it1, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int GP>
-static hipError_t scatter_gp(int mode, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0, int it1,
-                             int nb, hipStream_t s) {
-  if (mode == 0)
-    hipLaunchKernelGGL((k_scatter<GP, 0>), dim3(nb), dim3(64), lds, s, a, vis, partials, it0, it1);
+template <int GP, int MODE>
+static hipError_t scatter_m(int nkc, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0, int it1,
+                            int nb, hipStream_t s) {
+  const dim3 g(nb), b(64);
+  if (nkc == 1)
+    hipLaunchKernelGGL((k_scatter<GP, MODE, 1>), g, b, lds, s, a, vis, partials, it0, it1);
+  else if (nkc == 5)
+    hipLaunchKernelGGL((k_scatter<GP, MODE, 5>), g, b, lds, s, a, vis, partials, it0, it1);
   else
-    hipLaunchKernelGGL((k_scatter<GP, 1>), dim3(nb), dim3(64), lds, s, a, vis, partials, it0, it1);
+    hipLaunchKernelGGL((k_scatter<GP, MODE, 7>), g, b, lds, s, a, vis, partials, it0, it1);
   return hipGetLastError();
+}
+template <int GP>
+static hipError_t scatter_gp(int mode, int nkc, const GArgs& a, float2* vis, float2* partials, size_t lds, int it0,
+                             int it1, int nb, hipStream_t s) {
+  return mode == 0 ? scatter_m<GP, 0>(nkc, a, vis, partials, lds, it0, it1, nb, s)
+                   : scatter_m<GP, 1>(nkc, a, vis, partials, lds, it0, it1, nb, s);
 }
 
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials, int max_pitch,
@@ -980,12 +1084,13 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
   const int n = it1 - it0;
   if (n <= 0) return hipSuccess;
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
-  const size_t lds = (size_t)max_pitch * max_pitch * sizeof(float2);
+  const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // accumulator, spare cells
   if (lds > 65536) return hipErrorInvalidValue;
+  const int nkc = nk_class(max_pitch, a.T);
   switch (gprec) {
-    case 0: return scatter_gp<0>(mode, a, vis, partials, lds, it0, it1, nb, s);
-    case 1: return scatter_gp<1>(mode, a, vis, partials, lds, it0, it1, nb, s);
-    case 2: return scatter_gp<2>(mode, a, vis, partials, lds, it0, it1, nb, s);
+    case 0: return scatter_gp<0>(mode, nkc, a, vis, partials, lds, it0, it1, nb, s);
+    case 1: return scatter_gp<1>(mode, nkc, a, vis, partials, lds, it0, it1, nb, s);
+    case 2: return scatter_gp<2>(mode, nkc, a, vis, partials, lds, it0, it1, nb, s);
     default: return hipErrorInvalidValue;
   }
 }
