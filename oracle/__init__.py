@@ -11,6 +11,9 @@ Contents (each function cites the passage it follows):
   dual      l2-ball projection and the PDFB data-fidelity dual step (Section 2.2, eq. 2)
   nudft     direct non-uniform DFT (what the NUFFT of eq. 1 approximates)
   dr        visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5)
+  analysis  PSF, its peak normalisation eta_l and the residual image (the
+            residual-image definition among the evaluation metrics), and
+            ||Phi_l||^2 (dense definition and the power method)
 
 Everything is complex128 / float64.
 """
