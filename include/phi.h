@@ -210,6 +210,35 @@ phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
 phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
 
 /* ---------------------------------------------------------------------------
+ * Per-channel analysis quantities, all channels at once, asynchronous on
+ * `stream`.  They reuse the plan's forward and adjoint stages and its
+ * visibility scratch (calls on one plan must not overlap).
+ *
+ * PSF and its normalisation (the paper's residual-image definition among its
+ * evaluation metrics): delta is the image that is 1 at the phase centre
+ * (Ny/2, Nx/2) and 0 elsewhere; the PSF of channel l is Phi_l^dagger Phi_l
+ * delta and eta_l = 1 / (its value at the phase centre) makes it peak at 1.
+ * d_psf: float32 [L][Ny][Nx] out; d_peak: float64 [L] out (may be NULL).
+ */
+phi_status phi_psf(phi_plan plan, float* d_psf, double* d_peak, void* stream);
+
+/* Residual image r_l = eta_l Re Phi_l^dagger (y_l - Phi_l x_l) (same passage).
+ * d_x: float32 [L][Ny][Nx]; d_y: complex64 [M_tot] plan order; d_eta: float64
+ * [L] or NULL (=> 1); d_r: float32 [L][Ny][Nx] out. */
+phi_status phi_residual_image(phi_plan plan, const float* d_x, const void* d_y, const double* d_eta,
+                              float* d_r, void* stream);
+
+/* Power method for ||Phi_l||^2, the largest eigenvalue of Phi_l^dagger Phi_l
+ * (the bound on the step sizes of the primal-dual iteration, Section 2.2):
+ * x_l <- x_l / ||x_l||, then n_iter times x_l <- A x_l / ||A x_l|| with
+ * nu_l = ||A x_l|| (norms in FP64).  d_x: float32 [L][Ny][Nx], the start
+ * vector in (nonzero in every channel) and the last unit iterate out; d_tmp:
+ * float32 [L][Ny][Nx] scratch (distinct from d_x); d_nu: float64 [L] out;
+ * n_iter >= 1 (else PHI_ERR_RANGE). */
+phi_status phi_power_iteration(phi_plan plan, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu,
+                               void* stream);
+
+/* ---------------------------------------------------------------------------
  * Visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5) of one
  * data block, computed on the host in FP64 (a plan-time step, like packing G):
  *   H = G^H Theta^H Theta G, S = {p : H_pp > 0}, Lam_p = H_pp^(-1/2),

@@ -26,6 +26,7 @@ EXPORTS = [
     "phi_from_plan_order", "phi_forward", "phi_adjoint", "l2ball_dual_step",
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
     "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
+    "phi_psf", "phi_residual_image", "phi_power_iteration",
 ]
 
 

@@ -122,7 +122,7 @@ struct phi_plan_s {
   // workspace layout
   size_t off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
-         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, ws_bytes = 0;
+         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool bound = false;
   std::vector<char> g_loaded;
@@ -311,7 +311,8 @@ static void layout(phi_plan_s* p) {
   p->off_theta = take((size_t)p->nblk * 4);
   p->off_part = take(n_part * 8);
   p->off_norms = take(n_items * 16);
-  p->off_vscr = take((size_t)p->M * 8);   // scratch visibilities for the autotuner
+  p->off_vscr = take((size_t)p->M * 8);   // scratch visibilities (autotuner, analysis calls)
+  p->off_anal = take((size_t)p->L * (kNormChunks + 2) * 8);  // per-channel norm partials, norms
   p->off_scale = take((size_t)p->nblk * 8);
   p->off_flag = take(16);
   p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
@@ -1009,6 +1010,89 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;
+}
+
+
+// ------------------------------------------------------- analysis calls
+// Phi_l^dagger Phi_l x for every channel into out (visibility scratch between)
+static hipError_t normal_op(phi_plan_s* p, hipStream_t s, const float* x, float* out) {
+  float2* vs = p->at<float2>(p->off_vscr);
+  Runner r{p, s, false};
+  if (p->flags & PHI_PER_CHANNEL) {
+    for (int l = 0; l < p->L && r.err == hipSuccess; ++l) {
+      r.forward(x, vs, l, l + 1);
+      r.adjoint(vs, out, l, l + 1);
+    }
+  } else {
+    r.forward(x, vs, 0, p->L);
+    r.adjoint(vs, out, 0, p->L);
+  }
+  return r.err;
+}
+
+phi_status phi_psf(phi_plan p, float* d_psf, double* d_peak, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_psf) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  // delta into the output buffer, then Phi^dagger Phi in place (the forward
+  // pass has read x before the adjoint writes)
+  HIP_TRY(launch_delta(d_psf, p->L, p->Ny, p->Nx, s));
+  HIP_TRY(normal_op(p, s, d_psf, d_psf));
+  if (d_peak) HIP_TRY(launch_centre_value(d_psf, p->L, p->Ny, p->Nx, d_peak, s));
+  return PHI_OK;
+}
+
+phi_status phi_residual_image(phi_plan p, const float* d_x, const void* d_y, const double* d_eta, float* d_r,
+                              void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || !d_r || (p->M > 0 && !d_y)) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  float2* vs = p->at<float2>(p->off_vscr);
+  Runner r{p, s, false};
+  auto body = [&](int l0, int l1) {
+    r.forward(d_x, vs, l0, l1);
+    if (r.err == hipSuccess) r.err = launch_vis_residual(vs, (const float2*)d_y, p->M, s);
+    r.adjoint(vs, d_r, l0, l1);
+  };
+  if (p->flags & PHI_PER_CHANNEL) {
+    // the residual kernel covers every visibility; run it once, after all forwards
+    for (int l = 0; l < p->L && r.err == hipSuccess; ++l) r.forward(d_x, vs, l, l + 1);
+    if (r.err == hipSuccess) r.err = launch_vis_residual(vs, (const float2*)d_y, p->M, s);
+    for (int l = 0; l < p->L && r.err == hipSuccess; ++l) r.adjoint(vs, d_r, l, l + 1);
+  } else {
+    body(0, p->L);
+  }
+  if (r.err != hipSuccess) return PHI_ERR_HIP;
+  if (d_eta) HIP_TRY(launch_chan_scale(d_r, d_eta, p->L, (int64_t)p->Ny * p->Nx, s));
+  return PHI_OK;
+}
+
+phi_status phi_power_iteration(phi_plan p, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || !d_tmp || !d_nu || d_x == d_tmp) return PHI_ERR_ARG;
+  if (n_iter < 1) return PHI_ERR_RANGE;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = (int64_t)p->Ny * p->Nx;
+  double* part = p->at<double>(p->off_anal);
+  double* inv = part + (size_t)p->L * kNormChunks;
+  float* a = d_x;
+  float* b = d_tmp;
+  HIP_TRY(launch_chan_norm(a, p->L, n, part, nullptr, inv, s));
+  HIP_TRY(launch_chan_scale(a, inv, p->L, n, s));
+  for (int k = 0; k < n_iter; ++k) {
+    HIP_TRY(normal_op(p, s, a, b));
+    HIP_TRY(launch_chan_norm(b, p->L, n, part, d_nu, inv, s));
+    HIP_TRY(launch_chan_scale(b, inv, p->L, n, s));
+    std::swap(a, b);
+  }
+  if (a != d_x) HIP_TRY(hipMemcpyAsync(d_x, a, (size_t)p->L * n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return PHI_OK;
 }
 
 }  // extern "C"

@@ -91,6 +91,16 @@ hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, co
 hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n,
                           int to_plan, hipStream_t s);
 
+// analysis helpers (per-channel images are [L][n] float32)
+constexpr int kNormChunks = 256;
+hipError_t launch_delta(float* x, int L, int Ny, int Nx, hipStream_t s);
+hipError_t launch_vis_residual(float2* v, const float2* y, int64_t n, hipStream_t s);  // v <- y - v
+// part: [L][kNormChunks] scratch; norm, inv: [L] (either may be null)
+hipError_t launch_chan_norm(const float* x, int L, int64_t n, double* part, double* norm, double* inv,
+                            hipStream_t s);
+hipError_t launch_chan_scale(float* x, const double* f, int L, int64_t n, hipStream_t s);  // x_l *= f[l]
+hipError_t launch_centre_value(const float* x, int L, int Ny, int Nx, double* peak, hipStream_t s);
+
 bool fft_length_supported(int n);
 
 }  // namespace phi

@@ -911,6 +911,75 @@ __global__ __launch_bounds__(256) void k_permute(const float2* __restrict__ src,
     dst[perm[i]] = src[i];
 }
 
+// ---------------------------------------------------- analysis helpers
+// delta image per channel: 1 at the phase centre (Ny/2, Nx/2), 0 elsewhere
+__global__ __launch_bounds__(256) void k_delta(float* __restrict__ x, int Ny, int Nx) {
+  const int64_t n = (int64_t)Ny * Nx;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  x[(int64_t)blockIdx.y * n + i] = (i == (int64_t)(Ny / 2) * Nx + Nx / 2) ? 1.f : 0.f;
+}
+
+// v <- y - v (complex)
+__global__ __launch_bounds__(256) void k_vis_residual(float2* __restrict__ v, const float2* __restrict__ y,
+                                                      int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float2 a = v[i], b = y[i];
+  v[i] = make_float2(b.x - a.x, b.y - a.y);
+}
+
+// FP64 sum of squares of each channel image: work-group (c, l) sums the c-th
+// of kNormChunks contiguous slices of channel l in a fixed order
+__global__ __launch_bounds__(256) void k_chan_sumsq(const float* __restrict__ x, int64_t n,
+                                                    double* __restrict__ part) {
+  __shared__ double red[4];
+  const int c = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+  const int64_t per = (n + kNormChunks - 1) / kNormChunks;
+  const int64_t a = (int64_t)c * per, b = a + per < n ? a + per : n;
+  const float* __restrict__ xl = x + (int64_t)l * n;
+  double s = 0.0;
+  for (int64_t i = a + tid; i < b; i += 256) {
+    const double v = (double)xl[i];
+    s += v * v;
+  }
+  s = wave_sum_d(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  __syncthreads();
+  if (tid == 0) part[(int64_t)l * kNormChunks + c] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// norm_l = sqrt(sum of the channel's partials), inv_l = 1 / norm_l (0 if the
+// image is zero)
+__global__ __launch_bounds__(64) void k_chan_norm(const double* __restrict__ part, double* __restrict__ norm,
+                                                  double* __restrict__ inv) {
+  const int l = blockIdx.x, lane = threadIdx.x;
+  double s = 0.0;
+  for (int c = lane; c < kNormChunks; c += 64) s += part[(int64_t)l * kNormChunks + c];
+  s = wave_sum_d(s);
+  if (lane == 0) {
+    const double nv = sqrt(s);
+    if (norm) norm[l] = nv;
+    if (inv) inv[l] = nv > 0.0 ? 1.0 / nv : 0.0;
+  }
+}
+
+// x_l <- f_l x_l
+__global__ __launch_bounds__(256) void k_chan_scale(float* __restrict__ x, const double* __restrict__ f,
+                                                    int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int l = blockIdx.y;
+  x[(int64_t)l * n + i] *= (float)f[l];
+}
+
+// peak_l = psf_l at the phase centre
+__global__ __launch_bounds__(64) void k_centre_value(const float* __restrict__ x, int L, int Ny, int Nx,
+                                                     double* __restrict__ peak) {
+  const int l = blockIdx.x * 64 + threadIdx.x;
+  if (l < L) peak[l] = (double)x[(int64_t)l * Ny * Nx + (int64_t)(Ny / 2) * Nx + Nx / 2];
+}
+
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
 constexpr int kFftCells = 8192;  // N * W per work-group: 64 KiB of LDS
@@ -1114,6 +1183,35 @@ hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, i
                           hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_permute, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, perm, n, to_plan);
+  return hipGetLastError();
+}
+
+hipError_t launch_delta(float* x, int L, int Ny, int Nx, hipStream_t s) {
+  const int64_t n = (int64_t)Ny * Nx;
+  hipLaunchKernelGGL(k_delta, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, s, x, Ny, Nx);
+  return hipGetLastError();
+}
+
+hipError_t launch_vis_residual(float2* v, const float2* y, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vis_residual, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, v, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_chan_norm(const float* x, int L, int64_t n, double* part, double* norm, double* inv,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_chan_sumsq, dim3(kNormChunks, L), dim3(256), 0, s, x, n, part);
+  hipLaunchKernelGGL(k_chan_norm, dim3(L), dim3(64), 0, s, part, norm, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_chan_scale(float* x, const double* f, int L, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_chan_scale, dim3((unsigned)((n + 255) / 256), L), dim3(256), 0, s, x, f, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_centre_value(const float* x, int L, int Ny, int Nx, double* peak, hipStream_t s) {
+  hipLaunchKernelGGL(k_centre_value, dim3((L + 63) / 64), dim3(64), 0, s, x, L, Ny, Nx, peak);
   return hipGetLastError();
 }
 

@@ -171,6 +171,40 @@ class Plan:
                 "l2ball_dual_step")
         return grad, rho, res
 
+    def psf(self, out=None):
+        """(PSF images [L][Ny][Nx], peaks [L] float64): Phi_l^dagger Phi_l delta
+        and its value at the phase centre (eta_l = 1 / peak)."""
+        import torch
+        x = out if out is not None else torch.empty((self.L, self.ny, self.nx), dtype=torch.float32,
+                                                      device=self.device)
+        self._check_img(x)
+        peak = torch.empty(self.L, dtype=torch.float64, device=self.device)
+        L.check(self._lib.phi_psf(self._h, _dptr(x), _dptr(peak), _stream(torch, self.device)), "phi_psf")
+        return x, peak
+
+    def residual_image(self, x, y, eta=None, out=None):
+        """eta_l Re Phi_l^dagger (y_l - Phi_l x_l); y in plan order."""
+        import torch
+        self._check_img(x)
+        self._check_vis(y)
+        r = out if out is not None else torch.empty_like(x)
+        if eta is not None:
+            assert eta.dtype == torch.float64 and eta.numel() == self.L
+        L.check(self._lib.phi_residual_image(self._h, _dptr(x), _dptr(y), _dptr(eta), _dptr(r),
+                                             _stream(torch, self.device)), "phi_residual_image")
+        return r
+
+    def power_iteration(self, x, n_iter, tmp=None):
+        """||Phi_l||^2 estimates (float64 [L]) after n_iter power steps; x (float32
+        [L][Ny][Nx], nonzero per channel) is replaced by the last unit iterate."""
+        import torch
+        self._check_img(x)
+        t = tmp if tmp is not None else torch.empty_like(x)
+        nu = torch.empty(self.L, dtype=torch.float64, device=self.device)
+        L.check(self._lib.phi_power_iteration(self._h, _dptr(x), _dptr(t), int(n_iter), _dptr(nu),
+                                              _stream(torch, self.device)), "phi_power_iteration")
+        return nu
+
     def check(self):
         import torch
         L.check(self._lib.phi_plan_check(self._h, _stream(torch, self.device)), "phi_plan_check")

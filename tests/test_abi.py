@@ -89,6 +89,11 @@ def test_create_null_and_ok():
     # calls in the wrong order or with bad buffers fail before touching HIP
     assert lib.phi_forward(h, ctypes.c_void_p(16), ctypes.c_void_p(16), None) == -8
     assert lib.l2ball_dual_step(h, *([ctypes.c_void_p(16)] * 8), None) == -8
+    assert lib.phi_psf(h, ctypes.c_void_p(16), None, None) == -8
+    assert lib.phi_residual_image(h, *([ctypes.c_void_p(16)] * 4), None) == -8
+    assert lib.phi_power_iteration(h, ctypes.c_void_p(16), ctypes.c_void_p(32), 3, ctypes.c_void_p(64), None) == -8
+    assert lib.phi_psf(None, ctypes.c_void_p(16), None, None) == -1
+    assert lib.phi_power_iteration(None, None, None, 3, None, None) == -1
     assert lib.phi_plan_bind(h, None, n.value, None) == -1
     assert lib.phi_plan_bind(h, ctypes.c_void_p(256), n.value - 1, None) == -4
     assert lib.phi_plan_bind(h, ctypes.c_void_p(255), n.value, None) == -4
