@@ -75,7 +75,16 @@ typedef enum {
 typedef enum {
   PHI_G_C64 = 0,   /* complex float32                                   */
   PHI_G_F16 = 1,   /* complex float16 (RNE from the host values)        */
-  PHI_G_BF16 = 2   /* complex bfloat16 (RNE from the host values)       */
+  PHI_G_BF16 = 2,  /* complex bfloat16 (RNE from the host values)       */
+  PHI_G_KB = 3     /* no stored G: direction-independent Kaiser-Bessel
+                      rows psi(kappa_y - b_y - i) psi(kappa_x - b_x - j),
+                      psi(d) = I0(beta sqrt(1 - (2d/J)^2)) / I0(beta),
+                      evaluated in the kernels (FP32, I0 by Abramowitz &
+                      Stegun 9.8.1-9.8.2) from per-visibility kappa - b
+                      loaded with phi_plan_load_kb.  J = S of every
+                      visibility (one of 3, 5, 7, 9, 11), beta from Beatty
+                      et al. (2005) at 2x oversampling:
+                      pi sqrt((J/2)^2 1.5^2 - 0.8).                     */
 } phi_gprec;
 
 /* Host window element type accepted by phi_plan_load_g. */
@@ -97,7 +106,8 @@ typedef struct {
                                   channel-major                              */
   const int32_t* h_base;       /* [M_tot][2] window origin (b_y, b_x),
                                   0 <= b_y < Ky, 0 <= b_x < Kx; user order   */
-  const uint8_t* h_stencil;    /* [M_tot] window size S, odd, 1 <= S <= 21   */
+  const uint8_t* h_stencil;    /* [M_tot] window size S, odd, 1 <= S <= 21
+                                  (PHI_G_KB: one J in {3, 5, 7, 9, 11})      */
   const double* h_theta;       /* [sum B] whitening theta_b > 0 (NULL => 1)  */
   const double* h_scale_y;     /* [Ny] Z scale s_y (deapodisation)           */
   const double* h_scale_x;     /* [Nx] Z scale s_x                           */
@@ -146,6 +156,16 @@ phi_status phi_plan_bind(phi_plan plan, void* d_workspace, size_t bytes, void* s
  * with respect to h_windows (it can be freed on return). */
 phi_status phi_plan_load_g(phi_plan plan, int64_t block, const void* h_windows,
                            int32_t host_type, void* stream);
+
+/* Kaiser-Bessel mode (g_prec = PHI_G_KB): load block `block`'s continuous
+ * grid coordinates h_kappa [n][2] = (kappa_y, kappa_x) (host FP64, user
+ * order, kappa = omega K / (2 pi) in grid cells, any period).  The window
+ * origin floor(kappa - J/2) + 1 of every visibility must equal, mod K, the
+ * origin given at plan creation, else PHI_ERR_RANGE (nothing is loaded);
+ * non-finite kappa: PHI_ERR_RANGE.  The plan keeps kappa - b in FP32.  On a
+ * plan with stored G this call returns PHI_ERR_STATE, as phi_plan_load_g
+ * does on a Kaiser-Bessel plan.  Synchronous with respect to h_kappa. */
+phi_status phi_plan_load_kb(phi_plan plan, int64_t block, const double* h_kappa, void* stream);
 
 /* Replace the per-block whitening scalars (host [sum B], > 0). */
 phi_status phi_plan_set_theta(phi_plan plan, const double* h_theta, void* stream);

@@ -15,7 +15,7 @@ STATUS = {
     -4: "PHI_ERR_WORKSPACE", -5: "PHI_ERR_NONFINITE", -6: "PHI_ERR_HIP",
     -7: "PHI_ERR_UNSUPPORTED", -8: "PHI_ERR_STATE",
 }
-G_PREC = {"c64": 0, "f16": 1, "bf16": 2}
+G_PREC = {"c64": 0, "f16": 1, "bf16": 2, "kb": 3}
 HOST_C128, HOST_C64 = 0, 1
 PER_CHANNEL, GRAPH, PERSISTENT = 1, 2, 4
 
@@ -26,7 +26,7 @@ EXPORTS = [
     "phi_from_plan_order", "phi_forward", "phi_adjoint", "l2ball_dual_step",
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
     "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
-    "phi_psf", "phi_residual_image", "phi_power_iteration",
+    "phi_psf", "phi_residual_image", "phi_power_iteration", "phi_plan_load_kb",
 ]
 
 

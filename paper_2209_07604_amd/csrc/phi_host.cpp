@@ -122,7 +122,7 @@ struct phi_plan_s {
   // workspace layout
   size_t off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
-         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, ws_bytes = 0;
+         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0;
   char* ws = nullptr;
   bool bound = false;
   std::vector<char> g_loaded;
@@ -135,7 +135,11 @@ struct phi_plan_s {
   StageTimer timer;
   std::mutex mu;
 
-  size_t g_elem_bytes() const { return gprec == PHI_G_C64 ? 8 : 4; }
+  // G store bytes per tap (none in the Kaiser-Bessel mode, where taps are
+  // evaluated in the kernels from per-visibility fractional coordinates)
+  size_t g_elem_bytes() const { return gprec == PHI_G_KB ? 0 : gprec == PHI_G_C64 ? 8 : 4; }
+  int kb_J = 0;                 // window width of the Kaiser-Bessel mode
+  double kb_beta = 0.0, kb_inv_i0b = 0.0;
   template <typename T_>
   T_* at(size_t off) const { return reinterpret_cast<T_*>(ws + off); }
 };
@@ -147,7 +151,7 @@ static phi_status validate(const phi_desc* d) {
   if (d->ny < 8 || d->nx < 8 || (d->ny & 1) || (d->nx & 1)) return PHI_ERR_SHAPE;
   if (d->ny > 4096 || d->nx > 4096) return PHI_ERR_UNSUPPORTED;
   if (!fft_length_supported(2 * d->ny) || !fft_length_supported(2 * d->nx)) return PHI_ERR_UNSUPPORTED;
-  if (d->g_prec < PHI_G_C64 || d->g_prec > PHI_G_BF16) return PHI_ERR_ARG;
+  if (d->g_prec < PHI_G_C64 || d->g_prec > PHI_G_KB) return PHI_ERR_ARG;
   if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)) return PHI_ERR_ARG;
   if (d->persist_blocks < 0) return PHI_ERR_ARG;
   const int T = d->tile ? d->tile : 32;
@@ -173,6 +177,13 @@ static phi_status validate(const phi_desc* d) {
     if (S < 1 || S > kMaxS || !(S & 1) || S > Ky || S > Kx) return PHI_ERR_RANGE;
     const int by = d->h_base[2 * m], bx = d->h_base[2 * m + 1];
     if (by < 0 || by >= Ky || bx < 0 || bx >= Kx) return PHI_ERR_RANGE;
+  }
+  if (d->g_prec == PHI_G_KB && M > 0) {
+    // one Kaiser-Bessel width J for every visibility
+    const int J = d->h_stencil[0];
+    if (J != 3 && J != 5 && J != 7 && J != 9 && J != 11) return PHI_ERR_UNSUPPORTED;
+    for (int64_t m = 1; m < M; ++m)
+      if (d->h_stencil[m] != J) return PHI_ERR_RANGE;
   }
   if (d->h_theta)
     for (int64_t b = 0; b < nblk; ++b)
@@ -296,6 +307,7 @@ static void layout(phi_plan_s* p) {
     return r;
   };
   p->off_G = take((size_t)p->ntaps * p->g_elem_bytes());
+  p->off_frac = take(p->gprec == PHI_G_KB ? (size_t)p->M * 8 : 0);  // (kappa - b) per visibility, FP32
   p->off_meta = take((size_t)p->M * 4);
   p->off_perm = take((size_t)p->M * 4);
   size_t n_items = 0, n_tptr = 0, n_part = 0;
@@ -369,6 +381,7 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
   p->Ky = 2 * d->ny;
   p->Kx = 2 * d->nx;
   p->gprec = d->g_prec;
+
   p->flags = d->flags;
   p->persist = d->persist_blocks;
   p->n_blocks.assign(d->h_n_blocks, d->h_n_blocks + p->L);
@@ -386,6 +399,21 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
     M += p->blk_n[b];
   }
   p->M = M;
+  if (p->gprec == PHI_G_KB) {
+    // Beatty et al. (2005) shape parameter for width J at 2x oversampling,
+    // and 1 / I0(beta) from the power series sum_k ((beta/2)^k / k!)^2 (FP64)
+    p->kb_J = M > 0 ? d->h_stencil[0] : 7;
+    const double J = p->kb_J;
+    p->kb_beta = M_PI * std::sqrt((J / 2.0) * (J / 2.0) * 1.5 * 1.5 - 0.8);
+    const double h = p->kb_beta / 2.0;
+    double sum = 0.0, term = 1.0;
+    for (int k = 0; k < 400; ++k) {
+      if (k > 0) term *= (h / k) * (h / k);
+      sum += term;
+      if (k > 0 && term < 1e-18 * sum) break;
+    }
+    p->kb_inv_i0b = 1.0 / sum;
+  }
   p->theta.assign(p->nblk, 1.0);
   if (d->h_theta) p->theta.assign(d->h_theta, d->h_theta + p->nblk);
   p->sy.assign(d->h_scale_y, d->h_scale_y + p->Ny);
@@ -477,9 +505,12 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   const double K = (double)p->Ky * p->Kx, N = (double)p->Ny * p->Nx;
   // G read once per pass, 4 B of metadata per pass, v and y read, c written
   // (gather); c read, v+ written (scatter); grids 48 K + 8 N bytes per channel.
-  info->alg_bytes_gather = p->ntaps * bG + p->M * (4.0 + 24.0) + p->L * 8.0 * K;
-  info->alg_bytes_scatter = p->ntaps * bG + p->M * (4.0 + 16.0);
-  info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * 48.0 + p->L * (48.0 * K + 8.0 * N);
+  // the Kaiser-Bessel mode reads 8 B of fractional coordinates per
+  // visibility and pass instead of the taps
+  const double bV = p->gprec == PHI_G_KB ? 8.0 : 0.0;
+  info->alg_bytes_gather = p->ntaps * bG + p->M * (4.0 + bV + 24.0) + p->L * 8.0 * K;
+  info->alg_bytes_scatter = p->ntaps * bG + p->M * (4.0 + bV + 16.0);
+  info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * (48.0 + 2.0 * bV) + p->L * (48.0 * K + 8.0 * N);
   info->ky = p->Ky;
   info->kx = p->Kx;
   info->tile = p->W().T;
@@ -551,9 +582,59 @@ phi_status phi_plan_set_theta(phi_plan p, const double* h_theta, void* stream) {
   return PHI_OK;
 }
 
+phi_status phi_plan_load_kb(phi_plan p, int64_t block, const double* h_kappa, void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
+  if (p->gprec != PHI_G_KB || !p->bound) return PHI_ERR_STATE;
+  const int64_t u0 = p->blk_u0[block], n = p->blk_n[block];
+  if (n == 0) {
+    p->g_loaded[block] = 1;
+    return PHI_OK;
+  }
+  if (!h_kappa) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  float2* stage = nullptr;
+  HIP_TRY(hipHostMalloc((void**)&stage, (size_t)n * sizeof(float2), hipHostMallocDefault));
+  const double half = p->kb_J / 2.0;
+  std::atomic<int> bad{0};
+  parallel_for(n, [&](int64_t a, int64_t b) {
+    for (int64_t k = a; k < b; ++k) {
+      const int64_t ui = p->perm[u0 + k] - u0;  // user index inside the block
+      const double ky = h_kappa[2 * ui], kx = h_kappa[2 * ui + 1];
+      if (!std::isfinite(ky) || !std::isfinite(kx) || std::fabs(ky) > 1e7 || std::fabs(kx) > 1e7) {
+        bad = 1;
+        continue;
+      }
+      // window origin b = floor(kappa - J/2) + 1 must be the one given at
+      // plan creation (mod K); the kernels see only kappa - b
+      const double by = std::floor(ky - half) + 1.0, bx = std::floor(kx - half) + 1.0;
+      const int64_t my = (((int64_t)by % p->Ky) + p->Ky) % p->Ky, mx = (((int64_t)bx % p->Kx) + p->Kx) % p->Kx;
+      const uint32_t m = p->meta[u0 + k];
+      if (my != (int64_t)(m & 8191) || mx != (int64_t)((m >> 13) & 8191)) {
+        bad = 1;
+        continue;
+      }
+      stage[k] = make_float2((float)(ky - by), (float)(kx - bx));
+    }
+  });
+  phi_status rc = PHI_OK;
+  if (bad) {
+    rc = PHI_ERR_RANGE;
+  } else if (hipMemcpyAsync(p->ws + p->off_frac + (size_t)u0 * sizeof(float2), stage, (size_t)n * sizeof(float2),
+                            hipMemcpyHostToDevice, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess) {
+    rc = PHI_ERR_HIP;
+  }
+  (void)hipHostFree(stage);
+  if (rc == PHI_OK) p->g_loaded[block] = 1;
+  return rc;
+}
+
 phi_status phi_plan_load_g(phi_plan p, int64_t block, const void* h_windows, int32_t host_type, void* stream) {
   if (!p) return PHI_ERR_ARG;
   if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
+  if (p->gprec == PHI_G_KB) return PHI_ERR_STATE;
   if (!h_windows && p->blk_n[block] > 0) return PHI_ERR_ARG;
   if (host_type != PHI_HOST_C128 && host_type != PHI_HOST_C64) return PHI_ERR_ARG;
   if (!p->bound) return PHI_ERR_STATE;
@@ -674,6 +755,10 @@ struct Runner {
     a.Ky = p->Ky;
     a.Kx = p->Kx;
     a.T = p->W().T;
+    a.frac = p->gprec == PHI_G_KB ? p->at<float2>(p->off_frac) : nullptr;
+    a.kb_J = p->kb_J;
+    a.kb_beta = (float)p->kb_beta;
+    a.kb_inv_i0b = (float)p->kb_inv_i0b;
     return a;
   }
   int persist_blocks() const {

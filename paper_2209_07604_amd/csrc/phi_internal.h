@@ -64,6 +64,11 @@ struct GArgs {
   float2* grid;             // [L][Ky][Kx]
   int Ky, Kx;
   int T;                    // tile edge of the items (pitch = T + Smax - 1)
+  // Kaiser-Bessel mode: per-visibility (kappa_y - b_y, kappa_x - b_x) in plan
+  // order, the width J, beta and 1 / I0(beta)
+  const float2* frac;
+  int kb_J;
+  float kb_beta, kb_inv_i0b;
 };
 
 // Kernel launchers (phi_kernels.hip).  All asynchronous on `s`.

@@ -792,6 +792,220 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
   }
 }
 
+// ------------------------------------------- Kaiser-Bessel rows in-kernel
+// G rows of direction-independent data are separable Kaiser-Bessel taps,
+// g(i, j) = psi(f_y - i) psi(f_x - j) with f = kappa - b the position of the
+// visibility relative to its window origin (f in [J/2 - 1, J/2)) and
+// psi(d) = I0(beta sqrt(1 - (2d/J)^2)) / I0(beta).  The taps are evaluated
+// here instead of being read from HBM.
+//
+// I0 (z >= 0) by the polynomial approximations of Abramowitz & Stegun
+// (Handbook of Mathematical Functions, 9.8.1 for z <= 3.75 and 9.8.2
+// above, |relative error| < 2e-7); both are evaluated and one is selected,
+// so lanes do not diverge.
+__device__ __forceinline__ float bessel_i0(float z) {
+  const float t = z * (1.f / 3.75f), u = t * t;
+  const float small =
+      1.f + u * (3.5156229f + u * (3.0899424f + u * (1.2067492f + u * (0.2659732f + u * (0.0360768f + u * 0.0045813f)))));
+  const float r = 3.75f / fmaxf(z, 3.75f);
+  const float p = 0.39894228f +
+                  r * (0.01328592f +
+                       r * (0.00225319f +
+                            r * (-0.00157565f +
+                                 r * (0.00916281f +
+                                      r * (-0.02057706f + r * (0.02635537f + r * (-0.01647633f + r * 0.00392377f)))))));
+  const float large = p * __expf(fminf(z, 80.f)) * rsqrtf(fmaxf(z, 3.75f));
+  return z <= 3.75f ? small : large;
+}
+
+// The J taps psi(f - i), i = 0..J-1, of one axis.
+template <int J>
+__device__ __forceinline__ void kb_axis(float f, float beta, float inv_i0b, float (&w)[J]) {
+#pragma unroll
+  for (int i = 0; i < J; ++i) {
+    const float d = (f - (float)i) * (2.f / (float)J);
+    const float t = fmaxf(1.f - d * d, 0.f);
+    w[i] = bessel_i0(beta * sqrtf(t)) * inv_i0b;
+  }
+}
+
+// Gather, one lane per visibility: each lane evaluates its 2J taps once and
+// sums its J x J window from the LDS copy of the item's grid region as
+// sum_i psi_y(i) sum_j psi_x(j) X(i, j).  kGatherWaves waves per work-group
+// share the tile and take 64-visibility chunks of the item in turn.
+template <int MODE, int J>
+__global__ __launch_bounds__(64 * kGatherWaves) void k_gather_kb(GArgs a, float2* __restrict__ vis,
+                                                                 const float2* __restrict__ yv,
+                                                                 double* __restrict__ item_norms, int it0, int it1) {
+  extern __shared__ float2 tile[];
+  __shared__ double s_norm[2 * kGatherWaves];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
+    const Item item = a.items[it];
+    const int P = item.pitch;
+    const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
+    for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
+      const int r = e / P, c = e - (e / P) * P;
+      int gr = item.ty0 + r, gc = item.tx0 + c;
+      gr -= (gr >= a.Ky) ? a.Ky : 0;
+      gc -= (gc >= a.Kx) ? a.Kx : 0;
+      tile[e] = grid[(size_t)gr * a.Kx + gc];
+    }
+    __syncthreads();
+    const float th = a.theta[item.blk];
+    float inv_sig = 1.f;
+    if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+    double rho2 = 0.0, res2 = 0.0;
+    for (int c0 = item.v0 + 64 * w; c0 < item.v1; c0 += 64 * kGatherWaves) {
+      const bool live = c0 + lane < item.v1;
+      const int v = live ? c0 + lane : item.v1 - 1;
+      const uint32_t m = a.meta[v];
+      const float2 fr = a.frac[v];
+      float2 vv = make_float2(0.f, 0.f), yy = vv;
+      if (MODE == 1) {
+        vv = vis[v];
+        yy = yv[v];
+      }
+      float py[J], px[J];
+      kb_axis<J>(fr.x, a.kb_beta, a.kb_inv_i0b, py);
+      kb_axis<J>(fr.y, a.kb_beta, a.kb_inv_i0b, px);
+      const char* t0 = reinterpret_cast<const char*>(tile) +
+                       (size_t)(((int)(m & 8191) - item.ty0) * P + ((int)((m >> 13) & 8191) - item.tx0)) * 8;
+      float ax = 0.f, ay = 0.f;
+#pragma unroll
+      for (int i = 0; i < J; ++i) {
+        const float2* row = reinterpret_cast<const float2*>(t0 + (size_t)i * P * 8);
+        float rx = 0.f, ry = 0.f;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float2 X = row[j];
+          rx = __builtin_fmaf(px[j], X.x, rx);
+          ry = __builtin_fmaf(px[j], X.y, ry);
+        }
+        ax = __builtin_fmaf(py[i], rx, ax);
+        ay = __builtin_fmaf(py[i], ry, ay);
+      }
+      if (live) {
+        const float sx = th * ax, sy = th * ay;
+        if (MODE == 0) {
+          vis[v] = make_float2(sx, sy);
+        } else {
+          const float2 cc = make_float2(vv.x * inv_sig + sx - yy.x, vv.y * inv_sig + sy - yy.y);
+          vis[v] = cc;
+          const double rx = (double)sx - (double)yy.x, ry = (double)sy - (double)yy.y;
+          rho2 += (double)cc.x * (double)cc.x + (double)cc.y * (double)cc.y;
+          res2 += rx * rx + ry * ry;
+        }
+      }
+    }
+    if (MODE == 1) {
+      rho2 = wave_sum_d(rho2);
+      res2 = wave_sum_d(res2);
+      if (lane == 0) {
+        s_norm[2 * w] = rho2;
+        s_norm[2 * w + 1] = res2;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        double r0 = 0.0, r1 = 0.0;
+        for (int k = 0; k < kGatherWaves; ++k) {
+          r0 += s_norm[2 * k];
+          r1 += s_norm[2 * k + 1];
+        }
+        item_norms[2 * (int64_t)it] = r0;
+        item_norms[2 * (int64_t)it + 1] = r1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Adjoint: one wave per item owns its LDS accumulator as in k_scatter.  Per
+// 64-visibility chunk, lane l evaluates visibility l's 2J taps into an LDS
+// table; then for each visibility in order the lanes span its J x J window
+// (lane t on tap (t / J, t mod J), a second step for J > 8) and read-add-write
+// distinct cells, with g = psi_y(i) psi_x(j) read from the table.
+template <int MODE, int J>
+__global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__ vis, float2* __restrict__ partials,
+                                                   int it0, int it1) {
+  constexpr int NKJ = (J * J + 63) / 64;
+  extern __shared__ float2 acc[];  // pitch^2 cells, then 64 spare cells
+  __shared__ float psi[64][2 * J];
+  const int lane = threadIdx.x;
+  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
+    const Item item = a.items[it];
+    const int P = item.pitch, PP = P * P;
+    for (int e = lane; e < PP; e += 64) acc[e] = make_float2(0.f, 0.f);
+    const float th = a.theta[item.blk];
+    float sc = 1.f;
+    if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
+    // this lane's taps (t / J, t mod J) per step, as LDS byte offsets from the
+    // window origin; lanes past the window use their spare cell
+    uint32_t off[NKJ];
+    int ti[NKJ], tj[NKJ];
+    bool on[NKJ];
+#pragma unroll
+    for (int k = 0; k < NKJ; ++k) {
+      const int t = k * 64 + lane;
+      on[k] = t < J * J;
+      ti[k] = on[k] ? t / J : 0;
+      tj[k] = on[k] ? t - (t / J) * J : 0;
+      off[k] = (uint32_t)(ti[k] * P + tj[k]) * 8u;
+    }
+    const uint32_t spare = (uint32_t)(PP + lane) * 8u;
+    char* accb = reinterpret_cast<char*>(acc);
+    for (int c0 = item.v0; c0 < item.v1; c0 += 64) {
+      const int n = min(64, item.v1 - c0);
+      const bool live = lane < n;
+      const int v = live ? c0 + lane : c0 + n - 1;
+      const uint32_t m = a.meta[v];
+      const float2 fr = a.frac[v];
+      float2 vv = vis[v];
+      if (MODE == 1) {
+        vv = make_float2(sc * vv.x, sc * vv.y);
+        if (live) vis[v] = vv;
+      }
+      const float avx = th * vv.x, avy = th * vv.y;
+      const uint32_t base_b =
+          (uint32_t)(((int)(m & 8191) - item.ty0) * P + ((int)((m >> 13) & 8191) - item.tx0)) * 8u;
+      float py[J], px[J];
+      kb_axis<J>(fr.x, a.kb_beta, a.kb_inv_i0b, py);
+      kb_axis<J>(fr.y, a.kb_beta, a.kb_inv_i0b, px);
+      __syncthreads();  // previous chunk's table reads are done
+#pragma unroll
+      for (int i = 0; i < J; ++i) {
+        psi[lane][i] = py[i];
+        psi[lane][J + i] = px[i];
+      }
+      __syncthreads();
+      for (int k = 0; k < n; ++k) {
+        const float vx = readlane_f(avx, k), vy = readlane_f(avy, k);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base_b, k);
+        float2 cur[NKJ];
+        uint32_t ad[NKJ];
+        float g[NKJ];
+#pragma unroll
+        for (int q = 0; q < NKJ; ++q) {
+          g[q] = psi[k][ti[q]] * psi[k][J + tj[q]];
+          ad[q] = on[q] ? b + off[q] : spare;
+          cur[q] = *reinterpret_cast<float2*>(accb + ad[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NKJ; ++q) {
+          cur[q].x = __builtin_fmaf(g[q], vx, cur[q].x);
+          cur[q].y = __builtin_fmaf(g[q], vy, cur[q].y);
+          *reinterpret_cast<float2*>(accb + ad[q]) = cur[q];
+        }
+      }
+    }
+    __syncthreads();
+    float2* out = partials + item.poff;
+    for (int e = lane; e < PP; e += 64) out[e] = acc[e];
+    __syncthreads();
+  }
+}
+
 // One work-group per (channel, tile): cell (r, c) of the tile is the
 // fixed-order sum of the tile partials covering it (its own tile's items and
 // those of the tiles up to `halo` tiles above/left, with wrap).  The partial
@@ -1120,6 +1334,26 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
   const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell
   if (lds > 65536) return hipErrorInvalidValue;
+  if (gprec == 3) {
+    const dim3 g(nb), b(64 * kGatherWaves);
+#define PHI_KB_G(JJ)                                                                                       \
+  case JJ:                                                                                                 \
+    if (mode == 0)                                                                                         \
+      hipLaunchKernelGGL((k_gather_kb<0, JJ>), g, b, lds, s, a, vis, y, item_norms, it0, it1);            \
+    else                                                                                                   \
+      hipLaunchKernelGGL((k_gather_kb<1, JJ>), g, b, lds, s, a, vis, y, item_norms, it0, it1);            \
+    return hipGetLastError();
+    switch (a.kb_J) {
+      PHI_KB_G(3)
+      PHI_KB_G(5)
+      PHI_KB_G(7)
+      PHI_KB_G(9)
+      PHI_KB_G(11)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef PHI_KB_G
+  }
   const int nkc = nk_class(max_pitch, a.T);
   switch (gprec) {
     case 0: return gather_gp<0>(mode, nkc, a, vis, y, item_norms, lds, it0, it1, nb, s);
@@ -1155,6 +1389,26 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
   const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // accumulator, spare cells
   if (lds > 65536) return hipErrorInvalidValue;
+  if (gprec == 3) {
+    const dim3 g(nb), b(64);
+#define PHI_KB_S(JJ)                                                                                      \
+  case JJ:                                                                                                \
+    if (mode == 0)                                                                                        \
+      hipLaunchKernelGGL((k_scatter_kb<0, JJ>), g, b, lds, s, a, vis, partials, it0, it1);               \
+    else                                                                                                  \
+      hipLaunchKernelGGL((k_scatter_kb<1, JJ>), g, b, lds, s, a, vis, partials, it0, it1);               \
+    return hipGetLastError();
+    switch (a.kb_J) {
+      PHI_KB_S(3)
+      PHI_KB_S(5)
+      PHI_KB_S(7)
+      PHI_KB_S(9)
+      PHI_KB_S(11)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef PHI_KB_S
+  }
   const int nkc = nk_class(max_pitch, a.T);
   switch (gprec) {
     case 0: return scatter_gp<0>(mode, nkc, a, vis, partials, lds, it0, it1, nb, s);

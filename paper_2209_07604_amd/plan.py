@@ -95,6 +95,13 @@ class Plan:
         L.check(self._lib.phi_plan_load_g(self._h, int(block), _ptr(w), kind, _stream(torch, self.device)),
                 "phi_plan_load_g")
 
+    def load_kb(self, block, kappa):
+        """Kaiser-Bessel mode: continuous grid coordinates [n, 2] (FP64, user order)."""
+        import torch
+        k = np.ascontiguousarray(kappa, dtype=np.float64).reshape(-1, 2)
+        L.check(self._lib.phi_plan_load_kb(self._h, int(block), _ptr(k), _stream(torch, self.device)),
+                "phi_plan_load_kb")
+
     def set_flags(self, flags):
         L.check(self._lib.phi_plan_set_flags(self._h, int(flags)), "phi_plan_set_flags")
 

@@ -97,6 +97,17 @@ class Case:
         n_vis = [blk.M for blk in self.data]
         p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, self.s_y, self.s_x, self.theta,
                  g_prec=g_prec, flags=flags, tile=tile, persist_blocks=persist_blocks, device=device)
-        for k, (w, off) in enumerate(self.wins):
-            p.load_g(k, w)
+        if g_prec == "kb":
+            # direction-independent rows: the kernels evaluate the Kaiser-Bessel
+            # taps from the continuous grid coordinates
+            for k, blk in enumerate(self.data):
+                p.load_kb(k, self.kappa(blk))
+        else:
+            for k, (w, off) in enumerate(self.wins):
+                p.load_g(k, w)
         return p
+
+    def kappa(self, blk):
+        """Continuous grid coordinates omega K / (2 pi) of a block, [M, 2]."""
+        K = np.array([self.prob.Ky, self.prob.Kx], dtype=np.float64)
+        return blk.omega * K / (2 * np.pi)

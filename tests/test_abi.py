@@ -61,7 +61,7 @@ def _create(L, lib, d):
     (dict(S=[7, 8, 7]), -3), (dict(S=[0, 7, 7]), -3), (dict(S=[23, 7, 7]), -3),
     (dict(base=[[0, 0], [64, 0], [0, 0]]), -3), (dict(base=[[0, 0], [0, -1], [0, 0]]), -3),
     (dict(theta=[0.0]), -3), (dict(theta=[np.nan]), -3),
-    (dict(g_prec=3), -1), (dict(flags=64), -1), (dict(tile=8), -1), (dict(tile=48), -1),
+    (dict(g_prec=4), -1), (dict(flags=64), -1), (dict(tile=8), -1), (dict(tile=48), -1),
     (dict(persist_blocks=-1), -1),
 ])
 def test_create_rejects(kw, code):
@@ -92,6 +92,7 @@ def test_create_null_and_ok():
     assert lib.phi_psf(h, ctypes.c_void_p(16), None, None) == -8
     assert lib.phi_residual_image(h, *([ctypes.c_void_p(16)] * 4), None) == -8
     assert lib.phi_power_iteration(h, ctypes.c_void_p(16), ctypes.c_void_p(32), 3, ctypes.c_void_p(64), None) == -8
+    assert lib.phi_plan_load_kb(h, 0, ctypes.c_void_p(16), None) == -8   # not a Kaiser-Bessel plan
     assert lib.phi_psf(None, ctypes.c_void_p(16), None, None) == -1
     assert lib.phi_power_iteration(None, None, None, 3, None, None) == -1
     assert lib.phi_plan_bind(h, None, n.value, None) == -1
@@ -121,3 +122,22 @@ def test_info_counts_follow_synthetic_problem():
     assert info.n_taps == int(np.sum(S.astype(np.int64) ** 2))
     assert info.n_vis_total == len(S)
     lib.phi_plan_destroy(h)
+
+
+def test_kaiser_bessel_mode_checks():
+    """PHI_G_KB: one width J in {3, 5, 7, 9, 11}; G loading calls are mode-specific."""
+    L, lib = _lib()
+    h = ctypes.c_void_p()
+    d, keep = _desc(L, n_vis=(3,), S=[7, 7, 9], g_prec=3)
+    assert lib.phi_plan_create(ctypes.byref(d), ctypes.byref(h)) == -3
+    d, keep = _desc(L, n_vis=(2,), S=[13, 13], g_prec=3)
+    assert lib.phi_plan_create(ctypes.byref(d), ctypes.byref(h)) == -7
+    d, keep = _desc(L, n_vis=(2,), S=[7, 7], g_prec=3)
+    assert lib.phi_plan_create(ctypes.byref(d), ctypes.byref(h)) == 0
+    info = L.Info()
+    assert lib.phi_plan_get_info(h, ctypes.byref(info)) == 0
+    assert info.g_bytes == 0
+    assert lib.phi_plan_load_g(h, 0, ctypes.c_void_p(16), 0, None) == -8
+    assert lib.phi_plan_load_kb(h, 0, ctypes.c_void_p(16), None) == -8   # not bound yet
+    assert lib.phi_plan_load_kb(h, 3, ctypes.c_void_p(16), None) == -3
+    assert lib.phi_plan_destroy(h) == 0
