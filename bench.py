@@ -9,7 +9,9 @@ grid), 1.5M visibilities per channel, w-projection stencils 7x7 .. 17x17,
 30 dB input SNR, synthetic (seeded) data shaped like the paper's wideband VLA
 data.  Forms timed on the same data: plain FP32 (complex64 G, every stage
 launched per channel), batched FP32, batched FP16-G (the headline), batched
-BF16-G; batched forms replay a hipGraph.
+BF16-G; batched forms replay a hipGraph.  On direction-independent workloads
+(one window size) the form batched_kb evaluates the Kaiser-Bessel taps in the
+kernels instead of reading stored G.
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -56,7 +58,9 @@ def traffic_for(kernel, launch_alg_bytes):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def generate(name, log_every=8, channels=0):
+def generate(name, log_every=8, channels=0, windows=True):
+    """Problem, per-block (base, S, windows or None) and per-block continuous
+    grid coordinates [M, 2] (for the Kaiser-Bessel form)."""
     import synth
     prob = synth.make_problem(name)
     if channels and channels < prob.L:
@@ -65,14 +69,16 @@ def generate(name, log_every=8, channels=0):
                                   n_vis=[prob.n_vis[l] for l in sel],
                                   nu=None if prob.nu is None else prob.nu[sel])
     t0 = time.time()
-    blocks = []
+    blocks, kappas = [], []
+    K = np.array([prob.Ky, prob.Kx], dtype=np.float64)
     for k, (l, b) in enumerate(prob.block_list()):
         blk = prob.block(l, b)
-        w, _ = blk.windows(np.complex64)
+        w = blk.windows(np.complex64)[0] if windows else None
         blocks.append((blk.base, blk.S, w))
+        kappas.append(blk.omega * K / (2 * np.pi))
         if k % log_every == 0:
             log("[bench] generated block %d/%d (%.0f s)" % (k + 1, len(prob.block_list()), time.time() - t0))
-    return prob, blocks
+    return prob, blocks, kappas
 
 
 def cpu_baseline(prob, plan, theta, budget_s=30.0):
@@ -213,30 +219,36 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    prob, blocks = generate(args.config, channels=args.channels)
+    forms = [f for f in args.forms.split(",") if f]
+    prob, blocks, kappas = generate(args.config, channels=args.channels,
+                                    windows=args.dr or any(not f.endswith("_kb") for f in forms))
     L = prob.L
     n_vis = [len(s) for (_, s, _) in blocks]
     base = np.concatenate([b for (b, _, _) in blocks])
     S = np.concatenate([s for (_, s, _) in blocks])
     s_y, s_x = prob.deapodisation()
     M = int(len(S))
-    forms = [f for f in args.forms.split(",") if f]
-    precs = sorted({f.split("_")[1] for f in forms}, key=["c64", "f16", "bf16"].index)
+    precs = sorted({f.split("_")[1] for f in forms}, key=["c64", "f16", "bf16", "kb"].index)
     plans = {}
     t0 = time.time()
     for prec in precs:
         p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
         for k, (_, _, w) in enumerate(blocks):
-            p.load_g(k, w)
+            if prec == "kb":
+                p.load_kb(k, kappas[k])   # taps evaluated in the kernels
+            else:
+                p.load_g(k, w)
         plans[prec] = p
         log("[bench] plan %s ready (%.0f s), info %s" % (prec, time.time() - t0, p.info()))
     if not args.dr:
         del blocks
+    del kappas
 
     # inputs: x~ = x/2, y = theta Phi0 x + n at 30 dB (theta from the c64 form), v ~ 0.1 CN
     gen = torch.Generator(device=dev)
     gen.manual_seed(220907604)
     x = torch.from_numpy(np.stack([prob.image(l) for l in range(L)])).to(dev)
+    log("[bench] images ready (%.0f s)" % (time.time() - t0))
     pref = plans[precs[0]]
     y0 = pref.forward(x)
     ch_of_blk = np.repeat(np.arange(L), prob.n_blocks)
@@ -247,6 +259,7 @@ def main():
         pw[ch_of_blk[k]] += y0h[starts[k]:starts[k + 1]].sum().item()
     m_ch = np.array([sum(m) for m in prob.n_vis], dtype=np.float64)
     theta_ch = 1.0 / np.sqrt(pw / m_ch * 1e-3)
+    log("[bench] noiseless data and channel powers ready (%.0f s)" % (time.time() - t0))
     theta = theta_ch[ch_of_blk]
     noise = torch.complex(torch.randn(M, generator=gen, device=dev), torch.randn(M, generator=gen, device=dev))
     noise = noise * (0.5 ** 0.5)
@@ -266,6 +279,7 @@ def main():
     eps = torch.tensor(eps_h, dtype=torch.float64, device=dev)
     nblk = len(n_vis)
     torch.cuda.synchronize()
+    log("[bench] inputs resident (%.0f s)" % (time.time() - t0))
 
     results = {}
     for form in forms:
@@ -284,11 +298,13 @@ def main():
                 prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
         flags_now = p.info()["persist_blocks"] and PERSISTENT
         p.set_flags((PER_CHANNEL if kind == "plain" else GRAPH) | flags_now)
+        log("[bench] %s: warm-up" % form)
         for _ in range(args.warmup):
             v.copy_(v0)
             p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
         v.copy_(v0)
         torch.cuda.synchronize()
+        log("[bench] %s: timing %d steps" % (form, args.steps))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t_wall = time.perf_counter()
         e0.record()
@@ -332,6 +348,9 @@ def main():
         log("[bench] calibration copy of %d MiB done" % args.calib_copy_mib)
         del src, dst
     head = "batched_f16" if "batched_f16" in results else forms[-1]
+    if "batched_kb" in results and "batched_f16" in results:
+        results["batched_kb"]["speedup_vs_batched_f16"] = (results["batched_f16"]["ms_per_step"] /
+                                                           results["batched_kb"]["ms_per_step"])
     r = results[head]
     info = r["info"]
     gather_ms, scatter_ms = r["stage_ms"]["gather"], r["stage_ms"]["scatter"]

@@ -112,6 +112,22 @@ class Problem:
 
     # ------------------------------------------------------------------ sky
     def _ref_image(self):
+        cache = self.__dict__.setdefault("_sky_cache", {})
+        if "ref" not in cache:
+            cache["ref"] = self._ref_image_draw()
+        return cache["ref"]
+
+    def _alpha(self):
+        """Spectral-index map in [0.5, 1] (smooth, seeded)."""
+        cache = self.__dict__.setdefault("_sky_cache", {})
+        if "alpha" not in cache:
+            rng = self.rng(10_001)
+            a = gaussian_filter(rng.standard_normal((self.Ny, self.Nx)), max(2.0, self.Ny / 16))
+            a = (a - a.min()) / max(a.max() - a.min(), 1e-30)
+            cache["alpha"] = 0.5 + 0.5 * a
+        return cache["alpha"]
+
+    def _ref_image_draw(self):
         rng = self.rng(10_000)
         Ny, Nx = self.Ny, self.Nx
         x = np.zeros((Ny, Nx))
@@ -138,11 +154,7 @@ class Problem:
         """Channel l of the sky cube, float32 [Ny, Nx], nonnegative."""
         x = self._ref_image()
         if self.L > 1:
-            rng = self.rng(10_001)
-            a = gaussian_filter(rng.standard_normal((self.Ny, self.Nx)), max(2.0, self.Ny / 16))
-            a = (a - a.min()) / max(a.max() - a.min(), 1e-30)
-            alpha = 0.5 + 0.5 * a
-            x = x * (self.nu[l] / self.nu[0]) ** (-alpha)
+            x = x * (self.nu[l] / self.nu[0]) ** (-self._alpha())
         return x.astype(np.float32)
 
     # ------------------------------------------------------------------ uv
