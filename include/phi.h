@@ -259,6 +259,70 @@ phi_status phi_power_iteration(phi_plan plan, float* d_x, float* d_tmp, int32_t 
                                void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Regularizer-free primal-dual forward-backward (PDFB) loop: eq. (2) with the
+ * regularization reduced to the non-negativity constraint on the image cube
+ * (Section 2.2), i.e. find x_l >= 0 with ||Phi_{l,b} x_l - y_{l,b}|| <=
+ * eps_{l,b}.  One iteration, data-fidelity dual update first:
+ *   v+  = l2ball_dual_step at x~ (gives grad_l = sum_b Re Phi_{l,b}^H v+_b)
+ *   x+  = max(x - tau_l grad_l, 0),  x~ = 2 x+ - x,  x <- x+
+ *   eps = phi_eps_update(...)        (only with an adaptive rule)
+ * It converges for tau_l ||sum_b sigma_b Phi_{l,b}^H Phi_{l,b}|| < 1, e.g.
+ * sigma_b = 1 / ||Phi_l||^2 (phi_power_iteration) and tau_l < 1.
+ *
+ * Adaptive l2 bounds (effective noise estimation, Section 3.3: update the
+ * noise-level estimates and l2 bounds during the iteration, fix them once the
+ * bounds are satisfied), with the update rule of Dabbech et al. (2018) that
+ * the paper cites for it.  Per block b of channel l whose bound is not fixed,
+ * after the primal update: since_b += 1; if freeze and res_b <= lambda_hi
+ * eps_b the bound is fixed; otherwise, if ||x+ - x||^2 < var_tol^2 ||x+||^2
+ * (channel l; a zero image never counts as settled), since_b >= min_gap and
+ * res_b is outside [lambda_lo eps_b, lambda_hi eps_b]:
+ *   eps_b <- lambda_mix res_b + (1 - lambda_mix) eps_b, since_b <- 0,
+ *   count_b += 1.
+ * res_b is the residual ||Phi_b x~ - y_b|| of the same iteration's dual step.
+ * Valid rules: 0 < lambda_lo <= 1 <= lambda_hi, 0 < lambda_mix <= 1,
+ * var_tol >= 0, min_gap >= 0, all finite (else PHI_ERR_RANGE).
+ */
+typedef struct {
+  double lambda_lo;    /* lower edge of the accepted band (e.g. 0.99)      */
+  double lambda_hi;    /* upper edge; also the fixing threshold (1.01)     */
+  double lambda_mix;   /* weight of the residual in the update (0.618)     */
+  double var_tol;      /* relative image variation that counts as settled  */
+  int32_t min_gap;     /* iterations between two updates of one block      */
+  int32_t freeze;      /* nonzero: fix a bound once res_b <= lambda_hi eps */
+} phi_eps_rule;
+
+/* Primal step for every channel (FP32 image arithmetic, NaN propagates):
+ * x+ = max(x - tau_l grad_l, 0), x~ = 2 x+ - x, then x <- x+.
+ * d_x, d_xt: float32 [L][Ny][Nx] in/out (x~ is only written);
+ * d_grad: float32 [L][Ny][Nx]; d_tau: float64 [L] (>= 0, not checked on the
+ * device); d_var: float64 [L][2] out, (||x+ - x||^2, ||x+||^2) in FP64 with a
+ * fixed summation order, or NULL.  d_x, d_xt and d_grad must be distinct. */
+phi_status phi_pdfb_primal(phi_plan plan, float* d_x, float* d_xt, const float* d_grad, const double* d_tau,
+                           double* d_var, void* stream);
+
+/* One application of the adaptive rule to every block.  d_res: float64
+ * [sum B] (res_b); d_var: float64 [L][2] from phi_pdfb_primal; d_eps:
+ * float64 [sum B] in/out; d_state: int32 [sum B][3] in/out (since, fixed,
+ * count), zero at the start of a run; rule: host struct, read during the
+ * call. */
+phi_status phi_eps_update(phi_plan plan, const double* d_res, const double* d_var, const phi_eps_rule* rule,
+                          double* d_eps, int32_t* d_state, void* stream);
+
+/* n_iter >= 1 PDFB iterations (above), asynchronous on `stream`, no host
+ * synchronisation.  d_x, d_xt: float32 [L][Ny][Nx] in/out (x~ = x at the
+ * start of a run); d_v: complex64 [M_tot] plan order, in/out; d_y, d_eps,
+ * d_sigma, d_rho, d_res: as for l2ball_dual_step (d_eps is updated in place
+ * when rule != NULL); d_tau: float64 [L]; d_grad: float32 [L][Ny][Nx]
+ * scratch (last iteration's grad on return); d_var: float64 [L][2] out;
+ * rule: NULL for fixed bounds, else d_state (int32 [sum B][3]) is required.
+ * d_rho, d_res and d_var hold the last iteration's values. */
+phi_status phi_pdfb_run(phi_plan plan, float* d_x, float* d_xt, void* d_v, const void* d_y, double* d_eps,
+                        const double* d_sigma, const double* d_tau, int32_t n_iter, const phi_eps_rule* rule,
+                        int32_t* d_state, float* d_grad, double* d_rho, double* d_res, double* d_var,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * Visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5) of one
  * data block, computed on the host in FP64 (a plan-time step, like packing G):
  *   H = G^H Theta^H Theta G, S = {p : H_pp > 0}, Lam_p = H_pp^(-1/2),

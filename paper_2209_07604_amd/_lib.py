@@ -27,6 +27,7 @@ EXPORTS = [
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
     "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
     "phi_psf", "phi_residual_image", "phi_power_iteration", "phi_plan_load_kb",
+    "phi_pdfb_primal", "phi_eps_update", "phi_pdfb_run",
 ]
 
 
@@ -58,6 +59,15 @@ class Info(ctypes.Structure):
         ("ky", ctypes.c_int32), ("kx", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
+    ]
+
+
+class EpsRule(ctypes.Structure):
+    """phi_eps_rule: the adaptive l2-bound rule."""
+    _fields_ = [
+        ("lambda_lo", ctypes.c_double), ("lambda_hi", ctypes.c_double),
+        ("lambda_mix", ctypes.c_double), ("var_tol", ctypes.c_double),
+        ("min_gap", ctypes.c_int32), ("freeze", ctypes.c_int32),
     ]
 
 
@@ -104,6 +114,9 @@ def load():
         "phi_dr_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
         "phi_dr_copy": [P, V, V, V, V, V, V],
         "phi_dr_destroy": [P],
+        "phi_pdfb_primal": [P, V, V, V, V, V, V],
+        "phi_eps_update": [P, V, V, ctypes.POINTER(EpsRule), V, V, V],
+        "phi_pdfb_run": [P, V, V, V, V, V, V, V, I32, ctypes.POINTER(EpsRule), V, V, V, V, V, V],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)

@@ -83,9 +83,9 @@ struct StageTimer {
   }
 };
 
-const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather", "finalize",
-                             "scatter",    "merge",      "colfft_inv", "rowfft_inv"};
-constexpr int kNumStages = 8;
+const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather",     "finalize",  "scatter",
+                             "merge",      "colfft_inv", "rowfft_inv", "pdfb_primal", "eps_update"};
+constexpr int kNumStages = 10;
 
 }  // namespace
 
@@ -324,7 +324,7 @@ static void layout(phi_plan_s* p) {
   p->off_part = take(n_part * 8);
   p->off_norms = take(n_items * 16);
   p->off_vscr = take((size_t)p->M * 8);   // scratch visibilities (autotuner, analysis calls)
-  p->off_anal = take((size_t)p->L * (kNormChunks + 2) * 8);  // per-channel norm partials, norms
+  p->off_anal = take((size_t)p->L * (2 * kNormChunks + 2) * 8);  // per-channel norm partials, norms
   p->off_scale = take((size_t)p->nblk * 8);
   p->off_flag = take(16);
   p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
@@ -1177,6 +1177,85 @@ phi_status phi_power_iteration(phi_plan p, float* d_x, float* d_tmp, int32_t n_i
     std::swap(a, b);
   }
   if (a != d_x) HIP_TRY(hipMemcpyAsync(d_x, a, (size_t)p->L * n * sizeof(float), hipMemcpyDeviceToDevice, s));
+  return PHI_OK;
+}
+
+// ------------------------------------------------------------- PDFB loop
+static bool rule_ok(const phi_eps_rule* r) {
+  const double v[4] = {r->lambda_lo, r->lambda_hi, r->lambda_mix, r->var_tol};
+  for (double x : v)
+    if (!std::isfinite(x)) return false;
+  return r->lambda_lo > 0.0 && r->lambda_lo <= 1.0 && r->lambda_hi >= 1.0 && r->lambda_mix > 0.0 &&
+         r->lambda_mix <= 1.0 && r->var_tol >= 0.0 && r->min_gap >= 0;
+}
+
+static phi_status primal_locked(phi_plan_s* p, hipStream_t s, float* d_x, float* d_xt, const float* d_grad,
+                                const double* d_tau, double* d_var) {
+  Runner r{p, s, p->timing};
+  r.stage(8, [&] {
+    return launch_pdfb_primal(d_x, d_xt, d_grad, d_tau, p->L, (int64_t)p->Ny * p->Nx,
+                              p->at<double>(p->off_anal), d_var, s);
+  });
+  return r.err == hipSuccess ? PHI_OK : PHI_ERR_HIP;
+}
+
+static phi_status eps_locked(phi_plan_s* p, hipStream_t s, const double* d_res, const double* d_var,
+                             const phi_eps_rule* rule, double* d_eps, int32_t* d_state) {
+  EpsRule er;
+  er.lo = rule->lambda_lo;
+  er.hi = rule->lambda_hi;
+  er.mix = rule->lambda_mix;
+  er.var_tol = rule->var_tol;
+  er.min_gap = rule->min_gap;
+  er.freeze = rule->freeze != 0;
+  Runner r{p, s, p->timing};
+  r.stage(9, [&] {
+    return launch_eps_update(d_res, d_var, p->at<BlockInfo>(p->off_binfo), (int)p->nblk, er, d_eps, d_state, s);
+  });
+  return r.err == hipSuccess ? PHI_OK : PHI_ERR_HIP;
+}
+
+phi_status phi_pdfb_primal(phi_plan p, float* d_x, float* d_xt, const float* d_grad, const double* d_tau,
+                           double* d_var, void* stream) {
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || !d_xt || !d_grad || !d_tau) return PHI_ERR_ARG;
+  if (d_x == d_xt || (const float*)d_x == d_grad || (const float*)d_xt == d_grad) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  return primal_locked(p, (hipStream_t)stream, d_x, d_xt, d_grad, d_tau, d_var);
+}
+
+phi_status phi_eps_update(phi_plan p, const double* d_res, const double* d_var, const phi_eps_rule* rule,
+                          double* d_eps, int32_t* d_state, void* stream) {
+  if (!p || !d_res || !d_var || !rule || !d_eps || !d_state) return PHI_ERR_ARG;
+  if (!rule_ok(rule)) return PHI_ERR_RANGE;
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  std::lock_guard<std::mutex> lk(p->mu);
+  return eps_locked(p, (hipStream_t)stream, d_res, d_var, rule, d_eps, d_state);
+}
+
+phi_status phi_pdfb_run(phi_plan p, float* d_x, float* d_xt, void* d_v, const void* d_y, double* d_eps,
+                        const double* d_sigma, const double* d_tau, int32_t n_iter, const phi_eps_rule* rule,
+                        int32_t* d_state, float* d_grad, double* d_rho, double* d_res, double* d_var,
+                        void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (rule && !rule_ok(rule)) return PHI_ERR_RANGE;
+  if (n_iter < 1) return PHI_ERR_RANGE;
+  const phi_status st = ready(p);
+  if (st != PHI_OK) return st;
+  if (!d_x || !d_xt || !d_grad || !d_tau || !d_eps || !d_var || (p->M > 0 && (!d_v || !d_y))) return PHI_ERR_ARG;
+  if (d_x == d_xt || d_x == d_grad || d_xt == d_grad) return PHI_ERR_ARG;
+  if (rule && (!d_state || !d_res)) return PHI_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  for (int k = 0; k < n_iter; ++k) {
+    phi_status e = l2ball_dual_step(p, d_xt, d_v, d_y, d_eps, d_sigma, d_grad, d_rho, d_res, stream);
+    if (e != PHI_OK) return e;
+    std::lock_guard<std::mutex> lk(p->mu);
+    e = primal_locked(p, s, d_x, d_xt, d_grad, d_tau, d_var);
+    if (e == PHI_OK && rule) e = eps_locked(p, s, d_res, d_var, rule, d_eps, d_state);
+    if (e != PHI_OK) return e;
+  }
   return PHI_OK;
 }
 

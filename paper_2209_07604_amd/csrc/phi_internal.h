@@ -106,6 +106,18 @@ hipError_t launch_chan_norm(const float* x, int L, int64_t n, double* part, doub
 hipError_t launch_chan_scale(float* x, const double* f, int L, int64_t n, hipStream_t s);  // x_l *= f[l]
 hipError_t launch_centre_value(const float* x, int L, int Ny, int Nx, double* peak, hipStream_t s);
 
+// PDFB primal step: x <- max(x - tau_l g, 0), xt <- 2 x+ - x; part: [L][kNormChunks][2]
+// scratch, var: [L][2] (||x+ - x||^2, ||x+||^2), may be null
+hipError_t launch_pdfb_primal(float* x, float* xt, const float* g, const double* tau, int L, int64_t n,
+                              double* part, double* var, hipStream_t s);
+// adaptive l2-bound rule over the blocks; state: [nblk][3] (since, fixed, count)
+struct EpsRule {
+  double lo, hi, mix, var_tol;
+  int min_gap, freeze;
+};
+hipError_t launch_eps_update(const double* res, const double* var, const BlockInfo* blocks, int nblk,
+                             EpsRule rule, double* eps, int32_t* state, hipStream_t s);
+
 bool fft_length_supported(int n);
 
 }  // namespace phi

@@ -1194,6 +1194,84 @@ __global__ __launch_bounds__(64) void k_centre_value(const float* __restrict__ x
   if (l < L) peak[l] = (double)x[(int64_t)l * Ny * Nx + (int64_t)(Ny / 2) * Nx + Nx / 2];
 }
 
+// ------------------------------------------------------------ PDFB loop
+// Primal step of the regularizer-free iteration: x+ = P_+(x - tau_l g) with
+// NaN kept (a NaN is neither < 0 nor clipped), x~ = 2 x+ - x, and FP64
+// partial sums of ||x+ - x||^2 and ||x+||^2 per (channel, chunk).
+__global__ __launch_bounds__(256) void k_pdfb_primal(float* __restrict__ x, float* __restrict__ xt,
+                                                     const float* __restrict__ g, const double* __restrict__ tau,
+                                                     int64_t n, double* __restrict__ part) {
+  __shared__ double red[2][4];
+  const int c = blockIdx.x, l = blockIdx.y, tid = threadIdx.x;
+  const int64_t per = (n + kNormChunks - 1) / kNormChunks;
+  const int64_t a = (int64_t)c * per, b = a + per < n ? a + per : n;
+  const int64_t off = (int64_t)l * n;
+  const float t = (float)tau[l];
+  double d2 = 0.0, n2 = 0.0;
+  for (int64_t i = off + a + tid; i < off + b; i += 256) {
+    const float xo = x[i];
+    const float u = xo - t * g[i];
+    const float xn = u < 0.f ? 0.f : u;
+    x[i] = xn;
+    xt[i] = 2.f * xn - xo;
+    const double dd = (double)xn - (double)xo;
+    d2 += dd * dd;
+    n2 += (double)xn * (double)xn;
+  }
+  d2 = wave_sum_d(d2);
+  n2 = wave_sum_d(n2);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = d2;
+    red[1][tid >> 6] = n2;
+  }
+  __syncthreads();
+  if (tid < 2) part[((int64_t)l * kNormChunks + c) * 2 + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+}
+
+// var_l = fixed-order sums of the channel's chunk partials
+__global__ __launch_bounds__(64) void k_pdfb_var(const double* __restrict__ part, double* __restrict__ var) {
+  const int l = blockIdx.x, lane = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int c = lane; c < kNormChunks; c += 64) {
+    s0 += part[((int64_t)l * kNormChunks + c) * 2];
+    s1 += part[((int64_t)l * kNormChunks + c) * 2 + 1];
+  }
+  s0 = wave_sum_d(s0);
+  s1 = wave_sum_d(s1);
+  if (lane == 0) {
+    var[2 * l] = s0;
+    var[2 * l + 1] = s1;
+  }
+}
+
+// Adaptive l2 bound of one block per lane (rule stated with phi_eps_rule).
+__global__ __launch_bounds__(64) void k_eps_update(const double* __restrict__ res, const double* __restrict__ var,
+                                                   const BlockInfo* __restrict__ blocks, int nblk, EpsRule rule,
+                                                   double* __restrict__ eps, int32_t* __restrict__ state) {
+  const int b = blockIdx.x * 64 + threadIdx.x;
+  if (b >= nblk) return;
+  int since = state[3 * b], fixed = state[3 * b + 1], count = state[3 * b + 2];
+  if (fixed) return;
+  since += 1;
+  const double r = res[b], e = eps[b];
+  if (rule.freeze && r <= rule.hi * e) {
+    fixed = 1;
+  } else {
+    const int l = blocks[b].chan;
+    const double d2 = var[2 * l], n2 = var[2 * l + 1];
+    const bool settled = n2 > 0.0 && d2 < rule.var_tol * rule.var_tol * n2;
+    const bool outside = r < rule.lo * e || r > rule.hi * e;
+    if (settled && outside && since >= rule.min_gap) {
+      eps[b] = rule.mix * r + (1.0 - rule.mix) * e;
+      since = 0;
+      count += 1;
+    }
+  }
+  state[3 * b] = since;
+  state[3 * b + 1] = fixed;
+  state[3 * b + 2] = count;
+}
+
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
 constexpr int kFftCells = 8192;  // N * W per work-group: 64 KiB of LDS
@@ -1466,6 +1544,22 @@ hipError_t launch_chan_scale(float* x, const double* f, int L, int64_t n, hipStr
 
 hipError_t launch_centre_value(const float* x, int L, int Ny, int Nx, double* peak, hipStream_t s) {
   hipLaunchKernelGGL(k_centre_value, dim3((L + 63) / 64), dim3(64), 0, s, x, L, Ny, Nx, peak);
+  return hipGetLastError();
+}
+
+hipError_t launch_pdfb_primal(float* x, float* xt, const float* g, const double* tau, int L, int64_t n,
+                              double* part, double* var, hipStream_t s) {
+  if (L <= 0 || n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pdfb_primal, dim3(kNormChunks, L), dim3(256), 0, s, x, xt, g, tau, n, part);
+  if (var) hipLaunchKernelGGL(k_pdfb_var, dim3(L), dim3(64), 0, s, part, var);
+  return hipGetLastError();
+}
+
+hipError_t launch_eps_update(const double* res, const double* var, const BlockInfo* blocks, int nblk,
+                             EpsRule rule, double* eps, int32_t* state, hipStream_t s) {
+  if (nblk <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eps_update, dim3((nblk + 63) / 64), dim3(64), 0, s, res, var, blocks, nblk, rule, eps,
+                     state);
   return hipGetLastError();
 }
 

@@ -212,6 +212,73 @@ class Plan:
                                               _stream(torch, self.device)), "phi_power_iteration")
         return nu
 
+    # ------------------------------------------------------------ PDFB loop
+    @staticmethod
+    def eps_rule(lambda_lo=0.99, lambda_hi=1.01, lambda_mix=0.618, var_tol=1e-3, min_gap=10, freeze=True):
+        """The adaptive l2-bound rule as the C struct (defaults as in the
+        header's example values)."""
+        r = L.EpsRule()
+        r.lambda_lo, r.lambda_hi, r.lambda_mix, r.var_tol = lambda_lo, lambda_hi, lambda_mix, var_tol
+        r.min_gap, r.freeze = int(min_gap), 1 if freeze else 0
+        return r
+
+    def _f64(self, t, n, what):
+        import torch
+        if t.dtype != torch.float64 or t.numel() != n or not t.is_contiguous():
+            raise ValueError("%s must be contiguous float64 [%d]" % (what, n))
+
+    def pdfb_primal(self, x, xt, grad, tau, var=None):
+        """x <- max(x - tau_l grad_l, 0), xt <- 2 x+ - x (in place); returns
+        var float64 [L][2] = (||x+ - x||^2, ||x+||^2)."""
+        import torch
+        for t in (x, xt, grad):
+            self._check_img(t)
+        self._f64(tau, self.L, "tau")
+        var = torch.empty((self.L, 2), dtype=torch.float64, device=self.device) if var is None else var
+        self._f64(var, 2 * self.L, "var")
+        L.check(self._lib.phi_pdfb_primal(self._h, _dptr(x), _dptr(xt), _dptr(grad), _dptr(tau), _dptr(var),
+                                          _stream(torch, self.device)), "phi_pdfb_primal")
+        return var
+
+    def eps_update(self, res, var, eps, state, rule):
+        """One application of the adaptive rule (eps, state updated in place)."""
+        import torch
+        self._f64(res, self.nblk, "res")
+        self._f64(eps, self.nblk, "eps")
+        self._f64(var, 2 * self.L, "var")
+        if state.dtype != torch.int32 or state.numel() != 3 * self.nblk:
+            raise ValueError("state must be int32 [sum B][3]")
+        L.check(self._lib.phi_eps_update(self._h, _dptr(res), _dptr(var), ctypes.byref(rule), _dptr(eps),
+                                         _dptr(state), _stream(torch, self.device)), "phi_eps_update")
+
+    def pdfb_run(self, x, xt, v, y, eps, tau, n_iter, sigma=None, rule=None, state=None, grad=None, rho=None,
+                 res=None, var=None):
+        """n_iter PDFB iterations in place on x, xt, v (and eps, state with a
+        rule).  Returns (grad, rho, res, var, state) of the last iteration."""
+        import torch
+        dev = self.device
+        self._check_img(x)
+        self._check_img(xt)
+        self._check_vis(v)
+        self._check_vis(y)
+        self._f64(eps, self.nblk, "eps")
+        self._f64(tau, self.L, "tau")
+        if sigma is not None:
+            self._f64(sigma, self.nblk, "sigma")
+        grad = torch.empty_like(x) if grad is None else grad
+        rho = torch.empty(self.nblk, dtype=torch.float64, device=dev) if rho is None else rho
+        res = torch.empty(self.nblk, dtype=torch.float64, device=dev) if res is None else res
+        var = torch.empty((self.L, 2), dtype=torch.float64, device=dev) if var is None else var
+        self._f64(var, 2 * self.L, "var")
+        if rule is not None and state is None:
+            state = torch.zeros((self.nblk, 3), dtype=torch.int32, device=dev)
+        L.check(self._lib.phi_pdfb_run(self._h, _dptr(x), _dptr(xt), _dptr(v), _dptr(y), _dptr(eps),
+                                       _dptr(sigma), _dptr(tau), int(n_iter),
+                                       ctypes.byref(rule) if rule is not None else None, _dptr(state),
+                                       _dptr(grad), _dptr(rho), _dptr(res), _dptr(var), _stream(torch, dev)),
+                "phi_pdfb_run")
+        return grad, rho, res, var, state
+
     def check(self):
         import torch
         L.check(self._lib.phi_plan_check(self._h, _stream(torch, self.device)), "phi_plan_check")

@@ -94,6 +94,24 @@ def test_create_null_and_ok():
     assert lib.phi_power_iteration(h, ctypes.c_void_p(16), ctypes.c_void_p(32), 3, ctypes.c_void_p(64), None) == -8
     assert lib.phi_plan_load_kb(h, 0, ctypes.c_void_p(16), None) == -8   # not a Kaiser-Bessel plan
     assert lib.phi_psf(None, ctypes.c_void_p(16), None, None) == -1
+    # PDFB calls: rule and iteration count are checked first, then the plan state
+    buf = [ctypes.c_void_p(16 * (k + 1)) for k in range(16)]
+    good = L.EpsRule(0.99, 1.01, 0.618, 1e-3, 10, 1)
+    assert lib.phi_pdfb_primal(h, buf[0], buf[1], buf[2], buf[3], None, None) == -8
+    assert lib.phi_eps_update(h, buf[0], buf[1], ctypes.byref(good), buf[2], buf[3], None) == -8
+    run = lambda n_iter, rule: lib.phi_pdfb_run(h, *buf[:7], n_iter, rule, *buf[7:13], None)
+    assert run(3, None) == -8 and run(3, ctypes.byref(good)) == -8
+    assert run(0, None) == -3
+    for bad in (dict(lambda_lo=0.0), dict(lambda_lo=1.2), dict(lambda_hi=0.9), dict(lambda_mix=0.0),
+                dict(lambda_mix=1.5), dict(var_tol=-1.0), dict(var_tol=np.inf), dict(min_gap=-1),
+                dict(lambda_hi=np.nan)):
+        r = L.EpsRule(0.99, 1.01, 0.618, 1e-3, 10, 1)
+        for k, v in bad.items():
+            setattr(r, k, v)
+        assert run(3, ctypes.byref(r)) == -3, bad
+        assert lib.phi_eps_update(h, buf[0], buf[1], ctypes.byref(r), buf[2], buf[3], None) == -3, bad
+    assert lib.phi_eps_update(h, buf[0], buf[1], None, buf[2], buf[3], None) == -1
+    assert lib.phi_pdfb_primal(None, buf[0], buf[1], buf[2], buf[3], None, None) == -1
     assert lib.phi_power_iteration(None, None, None, 3, None, None) == -1
     assert lib.phi_plan_bind(h, None, n.value, None) == -1
     assert lib.phi_plan_bind(h, ctypes.c_void_p(256), n.value - 1, None) == -4
