@@ -136,6 +136,81 @@ def cpu_baseline(prob, plan, theta, budget_s=30.0):
     return base, err
 
 
+def _event_ms(fn, n):
+    """Average milliseconds of fn() over n calls (HIP events on the current stream)."""
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / n
+
+
+def stream_copy_gbs(dev, mib=2048):
+    """Device-to-device copy rate (read + write bytes / time) of a plain
+    copy: the practical streaming bound on this GPU."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    ms = _event_ms(lambda: dst.copy_(src), 10)
+    del src, dst
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
+    """phi_forward and phi_adjoint alone, and the regularizer-free PDFB
+    iteration (dual step + primal step + adaptive bounds) on the same plan."""
+    import torch
+    L, nblk = p.L, p.nblk
+    yv = torch.empty(p.M, dtype=torch.complex64, device=dev)
+    img = torch.empty_like(x)
+    for _ in range(warmup):
+        p.forward(x, out=yv)
+        p.adjoint(yv, out=img)
+    torch.cuda.synchronize()
+    out = {"forward_ms": _event_ms(lambda: p.forward(x, out=yv), steps),
+           "adjoint_ms": _event_ms(lambda: p.adjoint(yv, out=img), steps)}
+    # step sizes: sigma_b = 1 / ||Phi_l||^2 (10 power steps), tau_l = 0.9
+    w = x.clone()
+    nu = p.power_iteration(w, 10, tmp=img)
+    ch = torch.repeat_interleave(torch.arange(L, device=dev), torch.tensor(p._n_blocks.astype(np.int64), device=dev))
+    sigma = (1.0 / nu)[ch].contiguous()
+    tau = torch.full((L,), 0.9, dtype=torch.float64, device=dev)
+    rule = p.eps_rule()
+    xi, xti, v, e = x.clone(), x.clone(), v0.clone(), eps.clone()
+    grad = torch.empty_like(x)
+    rho = torch.empty(nblk, dtype=torch.float64, device=dev)
+    res = torch.empty_like(rho)
+    var = torch.empty((L, 2), dtype=torch.float64, device=dev)
+    state = torch.zeros((nblk, 3), dtype=torch.int32, device=dev)
+
+    def run(n):
+        p.pdfb_run(xi, xti, v, y, e, tau, n, sigma=sigma, rule=rule, state=state, grad=grad, rho=rho, res=res,
+                   var=var)
+    run(warmup)
+    torch.cuda.synchronize()
+    ms = _event_ms(lambda: run(steps), 1) / steps
+    p.set_timing(True)
+    run(steps)
+    torch.cuda.synchronize()
+    p.set_timing(False)
+    stages, calls = p.get_timing()
+    px = L * p.ny * p.nx
+    prim_ms = stages["pdfb_primal"] / max(calls, 1)
+    out["pdfb"] = {"ms_per_iter": ms, "primal_ms": prim_ms, "eps_update_ms": stages["eps_update"] / max(calls, 1),
+                   "primal_alg_bytes": 16.0 * px,
+                   "primal_GBs": 16.0 * px / (prim_ms * 1e-3) / 1e9,
+                   "rule": "adaptive l2 bounds (lambda 0.99/1.01/0.618, var_tol 1e-3, min_gap 10)",
+                   "steps": "sigma_b = 1/||Phi_l||^2 (10 power steps), tau_l = 0.9"}
+    return out
+
+
 def run_dr(args, prob, blocks, theta, y_user, starts, s_y, s_x, results, dev):
     """Reduce every block (host, FP64) and time the reduced dual step with the
     same precision and launch form as the headline; returns a summary."""
@@ -348,6 +423,13 @@ def main():
         log("[bench] calibration copy of %d MiB done" % args.calib_copy_mib)
         del src, dst
     head = "batched_f16" if "batched_f16" in results else forms[-1]
+    hp = plans[head.split("_")[1]]
+    hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0))
+    log("[bench] %s: forward, adjoint and PDFB iterations" % head)
+    extras = time_extras(hp, x, xt, hp.to_plan(v_init), y_plan[head.split("_")[1]], eps, args.steps, args.warmup,
+                         dev)
+    copy_gbs = stream_copy_gbs(dev)
+    log("[bench] extras %s, stream copy %.0f GB/s" % (extras, copy_gbs))
     if "batched_kb" in results and "batched_f16" in results:
         results["batched_kb"]["speedup_vs_batched_f16"] = (results["batched_f16"]["ms_per_step"] /
                                                            results["batched_kb"]["ms_per_step"])
@@ -381,7 +463,10 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": dur * 1e3},
+                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs,
+                     "frac_of_stream_copy": achieved / copy_gbs},
+        "forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
+        "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
     }
     if "plain_c64" in results:
@@ -389,8 +474,6 @@ def main():
     if args.dr:
         line["dimensionality_reduction"] = line_dr
     if not args.no_cpu_baseline:
-        hp = plans[head.split("_")[1]]
-        hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0))
         line["cpu_baseline"], line["err_vs_fp64_" + head] = cpu_baseline(prob, hp, theta)
     print(json.dumps(line), flush=True)
 
