@@ -148,19 +148,23 @@ def _event_ms(fn, n):
     return e0.elapsed_time(e1) / n
 
 
-def stream_copy_gbs(dev, mib=2048):
-    """Device-to-device copy rate (read + write bytes / time) of a plain
-    copy: the practical streaming bound on this GPU."""
+def stream_rates(dev, mib=2048):
+    """Practical streaming bounds on this GPU, from plain library kernels on
+    a 2 GiB buffer: device copy (read + write bytes / time) and a full sum
+    (bytes read / time)."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
+    acc = torch.empty((), dtype=torch.float32, device=dev)
     for _ in range(3):
         dst.copy_(src)
+        torch.sum(src, out=acc)
     torch.cuda.synchronize()
-    ms = _event_ms(lambda: dst.copy_(src), 10)
+    copy_ms = _event_ms(lambda: dst.copy_(src), 10)
+    read_ms = _event_ms(lambda: torch.sum(src, out=acc), 10)
     del src, dst
-    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+    return 2.0 * n * 4 / (copy_ms * 1e-3) / 1e9, n * 4 / (read_ms * 1e-3) / 1e9
 
 
 def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
@@ -428,8 +432,9 @@ def main():
     log("[bench] %s: forward, adjoint and PDFB iterations" % head)
     extras = time_extras(hp, x, xt, hp.to_plan(v_init), y_plan[head.split("_")[1]], eps, args.steps, args.warmup,
                          dev)
-    copy_gbs = stream_copy_gbs(dev)
-    log("[bench] extras %s, stream copy %.0f GB/s" % (extras, copy_gbs))
+    # (not in counter runs: their only large copy must be the calibration copy)
+    copy_gbs, read_gbs = (None, None) if args.calib_copy_mib else stream_rates(dev)
+    log("[bench] extras %s, stream copy %s GB/s, read %s GB/s" % (extras, copy_gbs, read_gbs))
     if "batched_kb" in results and "batched_f16" in results:
         results["batched_kb"]["speedup_vs_batched_f16"] = (results["batched_f16"]["ms_per_step"] /
                                                            results["batched_kb"]["ms_per_step"])
@@ -463,8 +468,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs,
-                     "frac_of_stream_copy": achieved / copy_gbs},
+                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs, "stream_read_GBs": read_gbs,
+                     "frac_of_stream_read": achieved / read_gbs if read_gbs else None},
         "forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
         "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
