@@ -159,10 +159,10 @@ def stream_rates(dev, mib=2048):
     acc = torch.empty((), dtype=torch.float32, device=dev)
     for _ in range(3):
         dst.copy_(src)
-        torch.sum(src, out=acc)
+        torch.sum(src, dim=0, out=acc)
     torch.cuda.synchronize()
     copy_ms = _event_ms(lambda: dst.copy_(src), 10)
-    read_ms = _event_ms(lambda: torch.sum(src, out=acc), 10)
+    read_ms = _event_ms(lambda: torch.sum(src, dim=0, out=acc), 10)
     del src, dst
     return 2.0 * n * 4 / (copy_ms * 1e-3) / 1e9, n * 4 / (read_ms * 1e-3) / 1e9
 

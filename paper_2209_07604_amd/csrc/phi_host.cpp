@@ -306,7 +306,9 @@ static void layout(phi_plan_s* p) {
     o = align_up(o + std::max<size_t>(bytes, 1));
     return r;
   };
-  p->off_G = take((size_t)p->ntaps * p->g_elem_bytes());
+  // G, then kGPadTaps zero taps: a window's fetch reads 64 * NK taps from its
+  // first one, so the last windows read into this pad
+  p->off_G = take((size_t)(p->ntaps + kGPadTaps) * p->g_elem_bytes());
   p->off_frac = take(p->gprec == PHI_G_KB ? (size_t)p->M * 8 : 0);  // (kappa - b) per visibility, FP32
   p->off_meta = take((size_t)p->M * 4);
   p->off_perm = take((size_t)p->M * 4);
@@ -562,6 +564,8 @@ phi_status phi_plan_bind(phi_plan p, void* d_ws, size_t bytes, void* stream) {
   HIP_TRY(up(p->off_sx, fx.data(), fx.size() * 4));
   const int zero[4] = {0, 0, 0, 0};
   HIP_TRY(up(p->off_flag, zero, sizeof(zero)));
+  if (p->g_elem_bytes())
+    HIP_TRY(hipMemsetAsync(p->ws + p->off_G + p->ntaps * p->g_elem_bytes(), 0, kGPadTaps * p->g_elem_bytes(), s));
   HIP_TRY(hipStreamSynchronize(s));  // host vectors above are temporaries
   if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   p->bound = true;

@@ -96,6 +96,10 @@ hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, co
 hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n,
                           int to_plan, hipStream_t s);
 
+// Zero taps kept behind G: a window's fetch reads 64 * NK taps (NK <= 7)
+// from its first tap, past the window's end.
+constexpr int kGPadTaps = 7 * 64;
+
 // analysis helpers (per-channel images are [L][n] float32)
 constexpr int kNormChunks = 256;
 hipError_t launch_delta(float* x, int L, int Ny, int Nx, hipStream_t s);

@@ -372,20 +372,20 @@ __device__ __forceinline__ float4 lane_sum2(float p0, float p1, float q0, float 
 
 // One wave streams the G taps of consecutive windows of a work item.  Lanes
 // span the S*S taps of a window (row-major) in NK steps of 64 (NK = steps of
-// the item's largest window); lanes past a smaller window re-read its last
-// tap, so every fetch issues exactly NK loads.  Each fetch address is the
-// window's first tap (uniform) plus a per-lane 32-bit byte offset kept for
-// runs of equal S.  The window's metadata word comes from two 64-visibility
-// chunks held one per lane (the fetch runs up to D windows ahead).
+// the item's largest window), so every fetch issues exactly NK loads at
+// fixed per-lane offsets (k * 64 + lane taps) from the window's first tap
+// (uniform).  Lanes past a smaller window read the next window's taps (or the
+// zero pad behind G); their products meet the zero cell (gather) or the
+// lane's spare cell (scatter), so they never reach a result.  The window's
+// metadata word comes from two 64-visibility chunks held one per lane (the
+// fetch runs up to D windows ahead).
 template <int GP, int NK>
 struct GStream {
   using R = typename GRaw<GP>::T;
-  static constexpr uint32_t kEb = sizeof(R);
   const char* __restrict__ G;
   int64_t tap;      // next window's first tap
   int64_t tap_end;  // re-read target once the range is exhausted
-  int j, v1, S = -1;
-  uint32_t fto[NK];
+  int j, v1;
   __device__ __forceinline__ void fetch(R (&g)[NK], uint32_t& m, uint32_t mcur, uint32_t mnxt, int cb, int lane) {
     const bool live = j < v1;
     const int rel = j - cb;  // < 64 + D
@@ -394,14 +394,9 @@ struct GStream {
     const uint32_t mt = live ? (rel < 64 ? ma : mb) : 0u;
     m = mt;
     const int s = 2 * (int)(mt >> 26) + 1;
-    if (s != S) {
-      S = s;
+    const R* __restrict__ gp = reinterpret_cast<const R*>(G) + (live ? tap : tap_end);
 #pragma unroll
-      for (int k = 0; k < NK; ++k) fto[k] = (uint32_t)min(k * 64 + lane, s * s - 1) * kEb;
-    }
-    const char* gp = G + (live ? tap : tap_end) * (int64_t)kEb;
-#pragma unroll
-    for (int k = 0; k < NK; ++k) g[k] = *reinterpret_cast<const R*>(gp + fto[k]);
+    for (int k = 0; k < NK; ++k) g[k] = gp[k * 64 + lane];
     tap += live ? s * s : 0;
     ++j;
   }
@@ -603,13 +598,13 @@ template <int GP, int MODE, int NKM>
 __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* __restrict__ vis,
                                                               const float2* __restrict__ yv,
                                                               double* __restrict__ item_norms, int it0, int it1) {
-  extern __shared__ float2 tile[];
-  __shared__ double s_norm[2 * kGatherWaves];
+  extern __shared__ float2 tile[];  // P*P cells, a zero cell, then the wave norms
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
     const Item item = a.items[it];
     const int P = item.pitch;
+    double* s_norm = reinterpret_cast<double*>(tile + P * P + 1);
     // copy the item's grid region (rows ty0.., columns tx0.., wrapped)
     const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
     for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
@@ -837,13 +832,13 @@ template <int MODE, int J>
 __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_kb(GArgs a, float2* __restrict__ vis,
                                                                  const float2* __restrict__ yv,
                                                                  double* __restrict__ item_norms, int it0, int it1) {
-  extern __shared__ float2 tile[];
-  __shared__ double s_norm[2 * kGatherWaves];
+  extern __shared__ float2 tile[];  // P*P cells, a zero cell, then the wave norms
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
     const Item item = a.items[it];
     const int P = item.pitch;
+    double* s_norm = reinterpret_cast<double*>(tile + P * P + 1);
     const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
     for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
       const int r = e / P, c = e - (e / P) * P;
@@ -1410,7 +1405,7 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
   const int n = it1 - it0;
   if (n <= 0) return hipSuccess;
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
-  const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell
+  const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell, wave norms
   if (lds > 65536) return hipErrorInvalidValue;
   if (gprec == 3) {
     const dim3 g(nb), b(64 * kGatherWaves);
