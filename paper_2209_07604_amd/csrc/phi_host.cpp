@@ -256,10 +256,24 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
       it.v1 = (int32_t)v;
       it.ntap = (int32_t)taps;
       {
-        const int n = it.v1 - it.v0, q = (n + kGatherWaves - 1) / kGatherWaves;
+        // the gather's waves share the item: give each an equal share of the
+        // work, counted as S^2 taps plus 64 per window (the per-window cost of
+        // the lane reduction and the G fetch, in tap-equivalents)
+        const int64_t total = taps + 64 * (int64_t)(it.v1 - it.v0);
+        int64_t acc = 0;
+        int64_t m = it.v0;
         for (int w = 1; w < kGatherWaves; ++w) {
-          const int64_t m = std::min<int64_t>(it.v0 + (int64_t)w * q, it.v1);
+          const int64_t target = total * w / kGatherWaves;
+          while (m < it.v1 && acc + (int64_t)p->S_plan[m] * p->S_plan[m] + 64 <= target) {
+            acc += (int64_t)p->S_plan[m] * p->S_plan[m] + 64;
+            ++m;
+          }
+          it.wv[w - 1] = (int32_t)m;
           it.sub[w - 1] = (int32_t)(p->tap_off[m] - it.tap0);
+        }
+        for (int w = kGatherWaves; w < 4; ++w) {
+          it.wv[w - 1] = it.v1;
+          it.sub[w - 1] = (int32_t)taps;
         }
       }
       it.pitch = T + smax - 1;

@@ -29,11 +29,13 @@ struct Item {
   int32_t ty0, tx0;
   int32_t pitch;
   int32_t ntap;    // taps of the run (sum of S^2)
-  int32_t sub[3];  // taps before visibility v0 + w * ceil(n / W), w = 1..3
-                   // (where the gather's waves 1..3 start, W <= 4 waves)
+  int32_t sub[3];  // taps before visibility wv[w - 1], w = 1..3
   int32_t pad;
+  int32_t wv[3];   // plan-order visibility where the gather's wave w = 1..3
+                   // starts (W <= 4 waves; equal shares of S^2 + 64 per window)
+  int32_t pad2;
 };
-static_assert(sizeof(Item) == 64, "Item layout");
+static_assert(sizeof(Item) == 80, "Item layout");
 #ifndef PHI_GATHER_WAVES
 #define PHI_GATHER_WAVES 4
 #endif

@@ -461,7 +461,7 @@ struct Depth {
 };
 
 template <int GP, int MODE, int NK, int D>
-__device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
+__device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
                                             float2* __restrict__ vis, const float2* __restrict__ yv,
                                             double& rho2, double& res2, const float2* __restrict__ tile) {
   using R = typename GRaw<GP>::T;
@@ -588,6 +588,26 @@ __device__ __forceinline__ void gather_item(const GArgs& a, const Item& item, in
     }
   }
   if (cb < v1) flush();
+  return gs.tap;
+}
+
+// Step count (64-tap loads) of a window from its metadata word, and the end
+// of the run of windows from r0 that share step count k0 (scanned 64 windows
+// at a time).  Plans sort windows by S inside each 16 x 16 uv sub-tile, so a
+// wave's range holds a few such runs; each run is processed with its own
+// step count instead of the item's largest.
+__device__ __forceinline__ int meta_steps(uint32_t m) {
+  const int s = 2 * (int)(m >> 26) + 1;
+  return (s * s + 63) >> 6;
+}
+__device__ __forceinline__ int steps_run_end(const uint32_t* __restrict__ meta, int r0, int v1, int k0, int lane) {
+  for (int c = r0; c < v1; c += 64) {
+    const int i = c + lane;
+    const bool other = i < v1 && meta_steps(meta[min(i, v1 - 1)]) != k0;
+    const uint64_t b = __ballot(other);
+    if (b) return c + (int)__builtin_ctzll(b);
+  }
+  return v1;
 }
 
 // kGatherWaves waves per work-group share one LDS copy of the item's grid
@@ -616,20 +636,20 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
     }
     if (tid == 0) tile[P * P] = make_float2(0.f, 0.f);  // the zero cell
     __syncthreads();
-    const int n = item.v1 - item.v0, q = (n + kGatherWaves - 1) / kGatherWaves;
-    const int wv0 = min(item.v0 + w * q, item.v1), wv1 = min(item.v0 + (w + 1) * q, item.v1);
-    const int64_t wtap =
-        item.tap0 + (w == 0 ? 0 : w == 1 ? item.sub[0] : w == 2 ? item.sub[1] : item.sub[2]);
-    const int smax = P - a.T + 1;
-    const int nk = (smax * smax + 63) / 64;
+    // (selects, not indexing: a run-time index would move the item to scratch)
+    const int wv0 = w == 0 ? item.v0 : w == 1 ? item.wv[0] : w == 2 ? item.wv[1] : item.wv[2];
+    const int wv1 = w == kGatherWaves - 1 ? item.v1 : w == 0 ? item.wv[0] : w == 1 ? item.wv[1] : item.wv[2];
+    int64_t wtap = item.tap0 + (w == 0 ? 0 : w == 1 ? item.sub[0] : w == 2 ? item.sub[1] : item.sub[2]);
     double rho2 = 0.0, res2 = 0.0;
-    if (wv0 < wv1) {
-      switch (nk) {
-#define PHI_G_CASE(K)                                                                                      \
-  case K:                                                                                                  \
-    if constexpr (K <= NKM)                                                                                \
-      gather_item<GP, MODE, K, Depth<GP, K, PHI_GATHER_DEPTH_REGS>::value>(a, item, wv0, wv1, wtap, vis, \
-                                                                           yv, rho2, res2, tile);      \
+    for (int r0 = wv0; r0 < wv1;) {
+      const int k0 = meta_steps(a.meta[r0]);
+      const int r1 = steps_run_end(a.meta, r0, wv1, k0, lane);
+      switch (k0) {
+#define PHI_G_CASE(K)                                                                                  \
+  case K:                                                                                              \
+    if constexpr (K <= NKM)                                                                            \
+      wtap = gather_item<GP, MODE, K, Depth<GP, K, PHI_GATHER_DEPTH_REGS>::value>(a, item, r0, r1, wtap, \
+                                                                                  vis, yv, rho2, res2, tile); \
     break;
         PHI_G_CASE(1)
         PHI_G_CASE(2)
@@ -642,6 +662,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
         default:
           break;
       }
+      r0 = r1;
     }
     if (MODE == 1) {
       rho2 = wave_sum_d(rho2);
@@ -674,11 +695,11 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
 // per lane), so no step needs a divergent branch.  The G taps are prefetched
 // exactly as in the gather.
 template <int GP, int MODE, int NK, int D>
-__device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, float2* __restrict__ vis,
-                                             float2* __restrict__ acc) {
+__device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
+                                                float2* __restrict__ vis, float2* __restrict__ acc) {
   using R = typename GRaw<GP>::T;
   const int lane = threadIdx.x;
-  const int v0 = item.v0, v1 = item.v1, vlast = v1 - 1, P = item.pitch;
+  const int vlast = v1 - 1, P = item.pitch;
   const uint32_t park = (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
   const float th = a.theta[item.blk];
   float sc = 1.f;
@@ -701,7 +722,7 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
   float2 vraw = vis[min(cb + 64 + lane, vlast)];
   R gb[D][NK];
   uint32_t ms[D];
-  GStream<GP, NK> gs{static_cast<const char*>(a.G), item.tap0, item.tap0, v0, v1};
+  GStream<GP, NK> gs{static_cast<const char*>(a.G), tap0, tap0, v0, v1};
   TapLayout<NK> lay;
   auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
     if (i == cb + 64) {
@@ -749,6 +770,7 @@ __device__ __forceinline__ void scatter_item(const GArgs& a, const Item& item, f
 #pragma unroll
   for (int d = 0; d < D - 1; ++d)
     if (i + d < v1) step(gb[d], ms[d], i + d);
+  return gs.tap;
 }
 
 template <int GP, int MODE, int NKM>
@@ -761,24 +783,29 @@ __global__ __launch_bounds__(64) void k_scatter(GArgs a, float2* __restrict__ vi
     const int P = item.pitch, PP = P * P;
     for (int e = lane; e < PP; e += 64) acc[e] = make_float2(0.f, 0.f);
     __syncthreads();
-    const int smax = P - a.T + 1;
-    const int nk = (smax * smax + 63) / 64;
-    switch (nk) {
-#define PHI_S_CASE(K)                                                                                     \
-  case K:                                                                                                 \
-    if constexpr (K <= NKM)                                                                               \
-      scatter_item<GP, MODE, K, Depth<GP, K, PHI_SCATTER_DEPTH_REGS>::value>(a, item, vis, acc);      \
+    int64_t tap = item.tap0;
+    for (int r0 = item.v0; r0 < item.v1;) {
+      const int k0 = meta_steps(a.meta[r0]);
+      const int r1 = steps_run_end(a.meta, r0, item.v1, k0, lane);
+      switch (k0) {
+#define PHI_S_CASE(K)                                                                                   \
+  case K:                                                                                               \
+    if constexpr (K <= NKM)                                                                             \
+      tap = scatter_item<GP, MODE, K, Depth<GP, K, PHI_SCATTER_DEPTH_REGS>::value>(a, item, r0, r1, tap, vis, \
+                                                                                   acc);              \
     break;
-      PHI_S_CASE(1)
-      PHI_S_CASE(2)
-      PHI_S_CASE(3)
-      PHI_S_CASE(4)
-      PHI_S_CASE(5)
-      PHI_S_CASE(6)
-      PHI_S_CASE(7)
+        PHI_S_CASE(1)
+        PHI_S_CASE(2)
+        PHI_S_CASE(3)
+        PHI_S_CASE(4)
+        PHI_S_CASE(5)
+        PHI_S_CASE(6)
+        PHI_S_CASE(7)
 #undef PHI_S_CASE
-      default:
-        break;
+        default:
+          break;
+      }
+      r0 = r1;
     }
     __syncthreads();
     float2* out = partials + item.poff;
