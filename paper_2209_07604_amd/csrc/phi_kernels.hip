@@ -52,6 +52,33 @@ __device__ __forceinline__ float readlane_f(float v, int i) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
 
+// A wave-uniform 64-bit value, so that it stays in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// LDS byte addresses: the offset of a __shared__ buffer inside the
+// work-group's LDS, and complex loads / stores at such an offset.  Callers
+// fold the buffer offset into their per-lane offsets once, so each access is
+// a single address register with no further add.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+using lds_f32x2 = __attribute__((address_space(3))) f32x2;
+__device__ __forceinline__ uint32_t lds_offset(const float2* p) {
+  return (uint32_t)(uintptr_t)(const lds_f32x2*)(const f32x2*)p;
+}
+__device__ __forceinline__ float2 lds_load(uint32_t a) {
+  const f32x2 v = *(const lds_f32x2*)(uintptr_t)a;
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void lds_store(uint32_t a, float2 v) {
+  f32x2 w;
+  w.x = v.x;
+  w.y = v.y;
+  *(lds_f32x2*)(uintptr_t)a = w;
+}
+
 // Row and column of tap t of an S x S window: i = floor((t + 1/2) / S) in
 // FP32 with the hardware reciprocal is exact for t < 441, S <= 21 (the
 // quotient stays >= 1/(2S) away from an integer, the reciprocal's relative
@@ -167,7 +194,9 @@ constexpr int pick_radix(int rem) {
                         : 2;
 }
 
-template <int N, int W, int NT, bool INV, int R, int NS>
+// tw holds the twiddles exp(-2 pi i m / (N TS)); a sub-transform of length N
+// reads every TS-th one.
+template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1>
 __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw) {
   constexpr int STRIDE = N / R;
   constexpr int NB = STRIDE * W;
@@ -186,7 +215,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
         const int k = b % NS;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          float2 w = tw[k * TWS * r];
+          float2 w = tw[k * TWS * r * TS];
           if (INV) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
@@ -209,12 +238,12 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
   __syncthreads();
 }
 
-template <int N, int W, int NT, bool INV, int NS>
+template <int N, int W, int NT, bool INV, int NS, int TS = 1>
 __device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS);
-    fft_pass<N, W, NT, INV, R, NS>(buf, tw);
-    fft_run<N, W, NT, INV, NS * R>(buf, tw);
+    fft_pass<N, W, NT, INV, R, NS, TS>(buf, tw);
+    fft_run<N, W, NT, INV, NS * R, TS>(buf, tw);
   }
 }
 
@@ -302,6 +331,85 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
   for (int e = threadIdx.x; e < N * W; e += NT) {
     const int k = e / W, c = e % W;
     const int p = (k < N / 2 ? k : k - N) + Ny / 2;
+    if (p >= 0 && p < Ny) out[(size_t)p * Kx + c0 + c] = buf[e];
+  }
+}
+
+// Long columns in two passes (N = N1 N2; row n = n1 + N1 n2 of the input,
+// row k = k2 + N2 k1 of the output):
+//   X[k2 + N2 k1] = sum_n1 w_N1^(n1 k1) w_N^(n1 k2) sum_n2 x[n1 + N1 n2] w_N2^(n2 k2).
+// Pass A takes one n1 per work-group and transforms along n2, applies
+// w_N^(n1 k2) and stores row k2 + N2 n1 of the grid; pass B takes one k2 and
+// transforms rows k2 + N2 j (j = n1 -> k1) in place.  A work-group holds W
+// columns, so each row access is W * 8 contiguous bytes (one column per
+// work-group would be 8).  The inverse runs the same passes in reverse order
+// with conjugate twiddles.
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__ half, float2* __restrict__ grid,
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+  constexpr int N = N1 * N2;
+  __shared__ float2 buf[N2 * W];
+  const int np = Kx / W;
+  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  const float2* in = half + (size_t)l * Ny * Kx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+    const int p = (n < N / 2 ? n : n - N) + Ny / 2;
+    buf[e] = (p >= 0 && p < Ny) ? in[(size_t)p * Kx + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_run<N2, W, NT, false, 1, N1>(buf, tw);
+  float2* out = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int k2 = e / W, c = e % W;
+    out[(size_t)k2 * Kx + c0 + c] = cmul(buf[e], tw[n1 * k2]);
+  }
+}
+
+template <int N1, int N2, int W, int NT, bool INV>
+__global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, const float2* __restrict__ tw, int Kx,
+                                                  int l0) {
+  constexpr int N = N1 * N2;
+  __shared__ float2 buf[N1 * W];
+  const int np = Kx / W;
+  const int k2 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  float2* g = grid + (size_t)l * N * Kx + (size_t)k2 * Kx;
+  for (int e = threadIdx.x; e < N1 * W; e += NT) {
+    const int j = e / W, c = e % W;
+    buf[e] = g[(size_t)N2 * j * Kx + c0 + c];
+  }
+  __syncthreads();
+  fft_run<N1, W, NT, INV, 1, N2>(buf, tw);
+  for (int e = threadIdx.x; e < N1 * W; e += NT) {
+    const int j = e / W, c = e % W;
+    float2 v = buf[e];
+    if (INV) {  // j = n1: apply conj(w_N^(n1 k2)) before the pass along k2
+      float2 w = tw[j * k2];
+      w.y = -w.y;
+      v = cmul(v, w);
+    }
+    g[(size_t)N2 * j * Kx + c0 + c] = v;
+  }
+}
+
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__ grid, float2* __restrict__ half,
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+  constexpr int N = N1 * N2;
+  __shared__ float2 buf[N2 * W];
+  const int np = Kx / W;
+  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  const float2* in = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int k2 = e / W, c = e % W;
+    buf[e] = in[(size_t)k2 * Kx + c0 + c];
+  }
+  __syncthreads();
+  fft_run<N2, W, NT, true, 1, N1>(buf, tw);
+  float2* out = half + (size_t)l * Ny * Kx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+    const int p = (n < N / 2 ? n : n - N) + Ny / 2;
     if (p >= 0 && p < Ny) out[(size_t)p * Kx + c0 + c] = buf[e];
   }
 }
@@ -397,7 +505,7 @@ struct GStream {
     const R* __restrict__ gp = reinterpret_cast<const R*>(G) + (live ? tap : tap_end);
 #pragma unroll
     for (int k = 0; k < NK; ++k) g[k] = gp[k * 64 + lane];
-    tap += live ? s * s : 0;
+    tap = uniform64(tap + (live ? s * s : 0));
     ++j;
   }
 };
@@ -489,7 +597,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   }
   R gb[D][NK];
   uint32_t ms[D];
-  GStream<GP, NK> gs{static_cast<const char*>(a.G), tap0, tap0, v0, v1};
+  GStream<GP, NK> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
   TapLayout<NK> lay;
   float2 res = make_float2(0.f, 0.f);  // lane i: sum for visibility cb + i (theta applied at flush)
   auto flush = [&]() {
@@ -524,19 +632,19 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   };
   // this lane's partial (sum over its taps of g * X) for one window; lanes
   // past the window read the zero cell behind the tile
-  const uint32_t park = (uint32_t)(P * P) * 8u;
+  const uint32_t tb = lds_offset(tile);
+  const uint32_t park = tb + (uint32_t)(P * P) * 8u;
   auto partial = [&](const R(&g)[NK], uint32_t mt, float& ax, float& ay) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
-    const uint32_t base_b = (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+    const uint32_t base_b = tb + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
     ax = 0.f;
     ay = 0.f;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       if (k * 64 < S2) {
-        const float2 X =
-            *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(tile) + lay.addr(base_b, k, park));
+        const float2 X = lds_load(lay.addr(base_b, k, park));
         const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
         ax = __builtin_fmaf(gx, X.x, ax);
         ax = __builtin_fmaf(-gy, X.y, ax);
@@ -546,7 +654,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     }
   };
   auto place = [&](int i, float px, float py) {
-    const bool me = lane == i - cb;
+    const bool me = lane == i - cb;  // i - cb is wave-uniform
     res.x = me ? px : res.x;
     res.y = me ? py : res.y;
   };
@@ -700,7 +808,8 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
   using R = typename GRaw<GP>::T;
   const int lane = threadIdx.x;
   const int vlast = v1 - 1, P = item.pitch;
-  const uint32_t park = (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
+  const uint32_t ab = lds_offset(acc);
+  const uint32_t park = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
   const float th = a.theta[item.blk];
   float sc = 1.f;
   if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
@@ -722,7 +831,7 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
   float2 vraw = vis[min(cb + 64 + lane, vlast)];
   R gb[D][NK];
   uint32_t ms[D];
-  GStream<GP, NK> gs{static_cast<const char*>(a.G), tap0, tap0, v0, v1};
+  GStream<GP, NK> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
   TapLayout<NK> lay;
   auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
     if (i == cb + 64) {
@@ -737,14 +846,13 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
     const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
     const float vx = readlane_f(avc.x, i - cb), vy = readlane_f(avc.y, i - cb);
-    const uint32_t base_b = (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
-    char* accb = reinterpret_cast<char*>(acc);
+    const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
     // all steps of one window touch distinct cells: read them all, then add
     // and write, so the window costs one LDS round trip, not one per step
     float2 cur[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k)
-      if (k * 64 < S2) cur[k] = *reinterpret_cast<float2*>(accb + lay.addr(base_b, k, park));
+      if (k * 64 < S2) cur[k] = lds_load(lay.addr(base_b, k, park));
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       if (k * 64 < S2) {
@@ -753,7 +861,7 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
         cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
         cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
         cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
-        *reinterpret_cast<float2*>(accb + lay.addr(base_b, k, park)) = cur[k];
+        lds_store(lay.addr(base_b, k, park), cur[k]);
       }
     }
   };
@@ -1316,9 +1424,28 @@ template <int N>
 constexpr int col_width() {
   return (kFftCells / N) > 16 ? 16 : (kFftCells / N) < 1 ? 1 : kFftCells / N;
 }
+// Long columns: (N1, N2) of the two-pass transform, or (0, 0) for one pass.
+template <int N>
+constexpr int col_split1() {
+  return N == 3072 ? 48 : N == 4096 ? 64 : N == 5120 ? 40 : N == 6144 ? 48 : N == 8192 ? 64 : 0;
+}
+constexpr int kColW2 = 32;  // columns per work-group in the two-pass transform (divides
+                            // every valid Kx: image edges are multiples of 16)
+
 template <int N>
 hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int Ny, int Kx, int l0, int nl,
                         hipStream_t s) {
+  constexpr int N1 = col_split1<N>();
+  if constexpr (N1 > 0) {
+    constexpr int N2 = N / N1, W = kColW2;
+    if (Kx % W == 0) {
+      hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, kFftThreads>), dim3(N1 * (Kx / W), nl), dim3(kFftThreads), 0, s,
+                         half, grid, tw, Ny, Kx, l0);
+      hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, kFftThreads, false>), dim3(N2 * (Kx / W), nl), dim3(kFftThreads),
+                         0, s, grid, tw, Kx, l0);
+      return hipGetLastError();
+    }
+  }
   constexpr int W = col_width<N>();
   if (Kx % W) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_colfft_fwd<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, half, grid,
@@ -1328,6 +1455,19 @@ hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int 
 template <int N>
 hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int Ny, int Kx, int l0, int nl,
                         hipStream_t s) {
+  constexpr int N1 = col_split1<N>();
+  if constexpr (N1 > 0) {
+    constexpr int N2 = N / N1, W = kColW2;
+    if (Kx % W == 0) {
+      // the pass along k1 runs in place on the grid, which the adjoint no
+      // longer needs afterwards
+      hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, kFftThreads, true>), dim3(N2 * (Kx / W), nl), dim3(kFftThreads), 0,
+                         s, const_cast<float2*>(grid), tw, Kx, l0);
+      hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, kFftThreads>), dim3(N1 * (Kx / W), nl), dim3(kFftThreads), 0, s,
+                         grid, half, tw, Ny, Kx, l0);
+      return hipGetLastError();
+    }
+  }
   constexpr int W = col_width<N>();
   if (Kx % W) return hipErrorInvalidValue;
   hipLaunchKernelGGL((k_colfft_inv<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, grid, half,

@@ -1,0 +1,52 @@
+"""Long grid columns (Ky = 3072 ... 8192): the column transforms of these
+lengths run in two passes (N = N1 N2).  Tall, narrow images keep the FP64 oracle
+cheap while the column length is that of the 4096^2-image workloads.
+Forward, adjoint and the dual step against the oracle at the FP32 bound."""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from _cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# (Ny, Nx): Ky = 2 Ny (image edges are multiples of 16, so Kx is a multiple
+# of 32 and every such plan takes the two-pass transform)
+SHAPES = [(1536, 16), (2048, 16), (2560, 16), (3072, 16), (4096, 16), (4096, 32)]
+
+
+@pytest.mark.parametrize("ny,nx", SHAPES)
+def test_long_columns(ny, nx):
+    from test_gpu_parity import gpu_forward, gpu_adjoint, gpu_dual
+    import oracle
+    _say("[fft-long] Ny", ny, "Nx", nx)
+    prob = synth.make_problem("tiny", Ny=ny, Nx=nx, n_vis=[[3000]])
+    c = Case("long%d_%d" % (ny, nx), problem=prob)
+    plan = c.plan()
+    want = c.op.forward({l: x.astype(np.float64) for l, x in c.X.items()})
+    got = gpu_forward(c, plan)
+    e = rel_l2(np.concatenate(got), np.concatenate(want))
+    _say("  forward rel L2", e)
+    assert e <= 1e-5
+    want_a = c.op.adjoint(c.Y)
+    got_a = gpu_adjoint(c, plan, c.Y)
+    e = rel_l2(got_a[0], want_a[0])
+    _say("  adjoint rel L2", e)
+    assert e <= 1e-5
+    Vp_o, grad_o, rho_o, res_o = oracle.dual_step(c.op, {l: x.astype(np.float64) for l, x in c.Xt.items()},
+                                                  c.V, c.Y, c.eps)
+    Vp, grad, rho, res = gpu_dual(c, plan, c.V, c.eps, None)
+    assert rel_l2(rho, rho_o) <= 1e-5 and rel_l2(res, res_o) <= 1e-5
+    assert rel_l2(np.concatenate(Vp), np.concatenate(Vp_o)) <= 1e-5
+    e = rel_l2(grad[0], grad_o[0])
+    _say("  grad rel L2", e)
+    assert e <= 1e-5
