@@ -120,7 +120,7 @@ struct phi_plan_s {
   WorkList& W() { return cands[cur]; }
   const WorkList& W() const { return cands[cur]; }
   // workspace layout
-  size_t off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
+  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
          off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0;
   char* ws = nullptr;
@@ -342,6 +342,7 @@ static void layout(phi_plan_s* p) {
   p->off_vscr = take((size_t)p->M * 8);   // scratch visibilities (autotuner, analysis calls)
   p->off_anal = take((size_t)p->L * (2 * kNormChunks + 2) * 8);  // per-channel norm partials, norms
   p->off_scale = take((size_t)p->nblk * 8);
+  p->off_bpart = take((size_t)p->nblk * kFinChunks * 16);  // per-block chunk sums of the item norms
   p->off_flag = take(16);
   p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
   p->off_half = take((size_t)p->L * p->Ny * p->Kx * 8);
@@ -857,7 +858,8 @@ struct Runner {
                            persist_blocks(), s);
     });
     stage(3, [&] {
-      return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo), eps, rho, res,
+      return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),
+                             p->at<double>(p->off_bpart), eps, rho, res,
                              p->at<double>(p->off_scale), p->at<int>(p->off_flag), b0, b1 - b0, s);
     });
     stage(4, [&] {

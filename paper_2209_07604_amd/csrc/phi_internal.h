@@ -92,9 +92,10 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,
                         const TileEntry* entries, int Ky, int Kx, int T, int halo, int l0, int nl,
                         hipStream_t s);
-hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, const double* eps,
-                           double* rho, double* res, double* scale, int* flag, int b0, int nb,
-                           hipStream_t s);
+// block_part: [nblk][kFinChunks][2] scratch
+constexpr int kFinChunks = 64;
+hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, double* block_part, const double* eps,
+                           double* rho, double* res, double* scale, int* flag, int b0, int nb, hipStream_t s);
 hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n,
                           int to_plan, hipStream_t s);
 

@@ -1216,19 +1216,42 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
   }
 }
 
-// Per-block FP64 norms from the item partials (fixed order), then the
-// projection scale: 0 inside the ball, 1 - eps/rho outside.
-__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ item_norms,
-                                                 const BlockInfo* __restrict__ blocks,
-                                                 const double* __restrict__ eps, double* __restrict__ rho,
-                                                 double* __restrict__ res, double* __restrict__ scale,
-                                                 int* __restrict__ flag, int b0) {
-  const int b = b0 + blockIdx.x, lane = threadIdx.x;
+// Per-block FP64 norms from the item partials, in two fixed-order levels:
+// kFinChunks work-groups per block sum fixed chunks of its items, then one
+// wave per block sums the chunk partials and forms the projection scale:
+// 0 inside the ball, 1 - eps/rho outside.
+__global__ __launch_bounds__(256) void k_block_sums(const double* __restrict__ item_norms,
+                                                    const BlockInfo* __restrict__ blocks, double* __restrict__ part,
+                                                    int b0) {
+  __shared__ double red[2][4];
+  const int b = b0 + blockIdx.y, c = blockIdx.x, tid = threadIdx.x;
   const BlockInfo bi = blocks[b];
+  const int n = bi.item1 - bi.item0, per = (n + kFinChunks - 1) / kFinChunks;
+  const int i0 = bi.item0 + c * per, i1 = min(i0 + per, bi.item1);
   double s0 = 0.0, s1 = 0.0;
-  for (int it = bi.item0 + lane; it < bi.item1; it += 64) {
+  for (int it = i0 + tid; it < i1; it += 256) {
     s0 += item_norms[2 * (int64_t)it];
     s1 += item_norms[2 * (int64_t)it + 1];
+  }
+  s0 = wave_sum_d(s0);
+  s1 = wave_sum_d(s1);
+  if ((tid & 63) == 0) {
+    red[0][tid >> 6] = s0;
+    red[1][tid >> 6] = s1;
+  }
+  __syncthreads();
+  if (tid < 2)
+    part[((int64_t)b * kFinChunks + c) * 2 + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+}
+
+__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ part, const double* __restrict__ eps,
+                                                 double* __restrict__ rho, double* __restrict__ res,
+                                                 double* __restrict__ scale, int* __restrict__ flag, int b0) {
+  const int b = b0 + blockIdx.x, lane = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0;
+  for (int c = lane; c < kFinChunks; c += 64) {
+    s0 += part[((int64_t)b * kFinChunks + c) * 2];
+    s1 += part[((int64_t)b * kFinChunks + c) * 2 + 1];
   }
   s0 = wave_sum_d(s0);
   s1 = wave_sum_d(s1);
@@ -1404,19 +1427,25 @@ __global__ __launch_bounds__(64) void k_eps_update(const double* __restrict__ re
 
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
+// Threads of a row transform: a row of 4096 or more points fills 32-64 KiB of
+// LDS, so few work-groups fit on a compute unit; give each more waves.
+template <int N>
+constexpr int row_threads() {
+  return N >= 4096 ? 512 : kFftThreads;
+}
 constexpr int kFftCells = 8192;  // N * W per work-group: 64 KiB of LDS
 
 template <int N>
 hipError_t rowfft_fwd_n(const float* x, float2* half, const float* sy, const float* sx, const float2* tw,
                         int Ny, int Nx, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowfft_fwd<N, kFftThreads>), dim3(Ny, nl), dim3(kFftThreads), 0, s, x, half, sy, sx,
+  hipLaunchKernelGGL((k_rowfft_fwd<N, row_threads<N>()>), dim3(Ny, nl), dim3(row_threads<N>()), 0, s, x, half, sy, sx,
                      tw, Ny, Nx, l0);
   return hipGetLastError();
 }
 template <int N>
 hipError_t rowfft_inv_n(const float2* half, float* x, const float* sy, const float* sx, const float2* tw,
                         int Ny, int Nx, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowfft_inv<N, kFftThreads>), dim3(Ny, nl), dim3(kFftThreads), 0, s, half, x, sy, sx,
+  hipLaunchKernelGGL((k_rowfft_inv<N, row_threads<N>()>), dim3(Ny, nl), dim3(row_threads<N>()), 0, s, half, x, sy, sx,
                      tw, Ny, Nx, l0);
   return hipGetLastError();
 }
@@ -1666,10 +1695,11 @@ hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* til
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, const double* eps, double* rho,
-                           double* res, double* scale, int* flag, int b0, int nb, hipStream_t s) {
+hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, double* block_part, const double* eps,
+                           double* rho, double* res, double* scale, int* flag, int b0, int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, s, item_norms, blocks, eps, rho, res, scale, flag, b0);
+  hipLaunchKernelGGL(k_block_sums, dim3(kFinChunks, nb), dim3(256), 0, s, item_norms, blocks, block_part, b0);
+  hipLaunchKernelGGL(k_finalize, dim3(nb), dim3(64), 0, s, block_part, eps, rho, res, scale, flag, b0);
   return hipGetLastError();
 }
 

@@ -1,5 +1,6 @@
 """Long grid columns (Ky = 3072 ... 8192): the column transforms of these
-lengths run in two passes (N = N1 N2).  Tall, narrow images keep the FP64 oracle
+lengths run in two passes (N = N1 N2); long rows (Kx = 4096, 8192) run with
+512 threads per row.  Tall, narrow images keep the FP64 oracle
 cheap while the column length is that of the 4096^2-image workloads.
 Forward, adjoint and the dual step against the oracle at the FP32 bound."""
 import sys
@@ -21,11 +22,13 @@ def _say(*a):
 
 # (Ny, Nx): Ky = 2 Ny (image edges are multiples of 16, so Kx is a multiple
 # of 32 and every such plan takes the two-pass transform)
-SHAPES = [(1536, 16), (2048, 16), (2560, 16), (3072, 16), (4096, 16), (4096, 32)]
+SHAPES = [(1536, 16), (2048, 16), (2560, 16), (3072, 16), (4096, 16), (4096, 32),
+          # long rows (Kx = 4096, 8192): row transforms with 512 threads
+          (16, 2048), (16, 4096)]
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES)
-def test_long_columns(ny, nx):
+def test_long_transforms(ny, nx):
     from test_gpu_parity import gpu_forward, gpu_adjoint, gpu_dual
     import oracle
     _say("[fft-long] Ny", ny, "Nx", nx)
