@@ -14,6 +14,9 @@ Contents (each function cites the passage it follows):
   analysis  PSF, its peak normalisation eta_l and the residual image (the
             residual-image definition among the evaluation metrics), and
             ||Phi_l||^2 (dense definition and the power method)
+  gbuild    rows of G from per-visibility tables: Kaiser-Bessel kernel
+            convolved with the w-kernel and the antenna pair's DDE kernel
+            (Sections 3.1-3.2)
   pdfb      regularizer-free PDFB iteration (non-negativity only, Section 2.2)
             with the adaptive l2-bound rule of the effective noise
             estimation (Section 3.3)
