@@ -167,6 +167,52 @@ phi_status phi_plan_load_g(phi_plan plan, int64_t block, const void* h_windows,
  * does on a Kaiser-Bessel plan.  Synchronous with respect to h_kappa. */
 phi_status phi_plan_load_kb(phi_plan plan, int64_t block, const double* h_kappa, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Device-side G builder (Sections 3.1-3.2: each row of G is the
+ * interpolation kernel convolved with the Fourier kernels of the w-term and
+ * of the antenna pair's DDEs).  Rows are computed in FP64 on the GPU from
+ * per-visibility tables and stored, rounded once (RNE) to the plan's
+ * precision, into block `block`'s G in plan order: the same result
+ * phi_plan_load_g gives for the same FP64 windows.
+ *
+ * Row of visibility m (user order within the block):
+ *   psi(d) = I0(beta sqrt(1 - (2d/J)^2)) / I0(beta) (0 outside |d| <= J/2),
+ *     beta = pi sqrt((J/2)^2 1.5^2 - 0.8), sampled per axis at
+ *     kappa - (b + i), i = 0..J-1, b = floor(kappa - J/2) + 1;
+ *   w-kernel per axis, k = -h..h: c_k = cos^2(pi k / (2 (h + 1)))
+ *     exp(-i pi k^2 / (4 max(a, 1/2))), divided by sum_k c_k (h = 0: 1);
+ *   u = psi (*) c per axis (length J + 2h), window = outer(u_y, u_x),
+ *   then, with DDEs, window (*) (d_i (*) conj(flip(d_j))) (d: the antennas'
+ *     sa x sa kernels, pair edge sd = 2 sa - 1; sd = 1 without DDE);
+ *   S = J + 2h + sd - 1, first cell b - h - (sd - 1)/2 per axis (mod K).
+ * S and the first cell must equal those declared for the visibility at plan
+ * creation, else PHI_ERR_RANGE (the block's G is then undefined and the block
+ * counts as not loaded).  Synchronous.  Not available on PHI_G_KB plans
+ * (PHI_ERR_STATE).
+ */
+typedef struct {
+  int32_t J;       /* Kaiser-Bessel width: odd, 3..11                        */
+  int32_t n_ant;   /* antennas in d_dde (0 without DDEs)                     */
+  int32_t sa;      /* antenna kernel edge: odd, 1..7 (ignored without DDEs)  */
+  int32_t reserved;
+} phi_gbuild;
+
+/* d_kappa: float64 [n][2] device, (kappa_y, kappa_x) in grid cells, user
+ * order of the block (n = its visibility count); d_h: int32 [n] w half-widths
+ * >= 0; d_a: float64 [n] w-chirp parameters; d_ant: int32 [n][2] antenna
+ * indices (i, j) in [0, n_ant), or (-1, -1) for a row without DDE, or NULL
+ * for no DDEs at all; d_dde: complex128 [n_ant][sa][sa] (NULL iff d_ant is
+ * NULL).  All device pointers, read on `stream`. */
+phi_status phi_plan_build_g(phi_plan plan, int64_t block, const phi_gbuild* desc, const double* d_kappa,
+                            const int32_t* d_h, const double* d_a, const int32_t* d_ant, const void* d_dde,
+                            void* stream);
+
+/* Copy block `block`'s stored G to host memory in user order, S*S taps per
+ * visibility back to back, converted exactly from the stored precision to
+ * host_type (PHI_HOST_C128 or PHI_HOST_C64).  Synchronous.  PHI_ERR_STATE on
+ * a Kaiser-Bessel plan or a block not loaded. */
+phi_status phi_plan_read_g(phi_plan plan, int64_t block, void* h_windows, int32_t host_type, void* stream);
+
 /* Replace the per-block whitening scalars (host [sum B], > 0). */
 phi_status phi_plan_set_theta(phi_plan plan, const double* h_theta, void* stream);
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
     "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
     "phi_psf", "phi_residual_image", "phi_power_iteration", "phi_plan_load_kb",
-    "phi_pdfb_primal", "phi_eps_update", "phi_pdfb_run",
+    "phi_pdfb_primal", "phi_eps_update", "phi_pdfb_run", "phi_plan_build_g", "phi_plan_read_g",
 ]
 
 
@@ -60,6 +60,12 @@ class Info(ctypes.Structure):
         ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
     ]
+
+
+class GBuild(ctypes.Structure):
+    """phi_gbuild: Kaiser-Bessel width and the DDE table's shape."""
+    _fields_ = [("J", ctypes.c_int32), ("n_ant", ctypes.c_int32), ("sa", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class EpsRule(ctypes.Structure):
@@ -114,6 +120,8 @@ def load():
         "phi_dr_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
         "phi_dr_copy": [P, V, V, V, V, V, V],
         "phi_dr_destroy": [P],
+        "phi_plan_build_g": [P, I64, ctypes.POINTER(GBuild), V, V, V, V, V, V],
+        "phi_plan_read_g": [P, I64, V, I32, V],
         "phi_pdfb_primal": [P, V, V, V, V, V, V],
         "phi_eps_update": [P, V, V, ctypes.POINTER(EpsRule), V, V, V],
         "phi_pdfb_run": [P, V, V, V, V, V, V, V, I32, ctypes.POINTER(EpsRule), V, V, V, V, V, V],

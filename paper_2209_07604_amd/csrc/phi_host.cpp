@@ -1279,4 +1279,127 @@ phi_status phi_pdfb_run(phi_plan p, float* d_x, float* d_xt, void* d_v, const vo
   return PHI_OK;
 }
 
+// ------------------------------------------------------------- G builder
+static double host_i0(double z) {  // power series sum_k ((z/2)^k / k!)^2
+  const double h = z / 2.0;
+  double sum = 0.0, term = 1.0;
+  for (int k = 0; k < 400; ++k) {
+    if (k > 0) term *= (h / k) * (h / k);
+    sum += term;
+    if (k > 0 && term < 1e-18 * sum) break;
+  }
+  return sum;
+}
+
+phi_status phi_plan_build_g(phi_plan p, int64_t block, const phi_gbuild* desc, const double* d_kappa,
+                            const int32_t* d_h, const double* d_a, const int32_t* d_ant, const void* d_dde,
+                            void* stream) {
+  if (!p || !desc) return PHI_ERR_ARG;
+  if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
+  if (p->gprec == PHI_G_KB) return PHI_ERR_STATE;
+  if (desc->J < 3 || desc->J > 11 || (desc->J & 1) == 0) return PHI_ERR_RANGE;
+  if ((d_ant == nullptr) != (d_dde == nullptr)) return PHI_ERR_ARG;
+  if (d_ant && (desc->n_ant < 1 || desc->sa < 1 || desc->sa > 7 || (desc->sa & 1) == 0)) return PHI_ERR_RANGE;
+  const int64_t n = p->blk_n[block];
+  if (n > 0 && (!d_kappa || !d_h || !d_a)) return PHI_ERR_ARG;
+  if (!p->bound) return PHI_ERR_STATE;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  p->g_loaded[block] = 0;
+  if (n == 0) {
+    p->g_loaded[block] = 1;
+    return PHI_OK;
+  }
+  BuildArgs a;
+  a.items = p->at<Item>(p->off_items);
+  a.meta = p->at<uint32_t>(p->off_meta);
+  a.perm = p->at<int32_t>(p->off_perm);
+  a.G = p->ws + p->off_G;
+  a.gprec = p->gprec;
+  a.kappa = d_kappa;
+  a.h = d_h;
+  a.a = d_a;
+  a.ant = d_ant;
+  a.dde = static_cast<const double*>(d_dde);
+  a.n_ant = d_ant ? desc->n_ant : 0;
+  a.sa = d_ant ? desc->sa : 1;
+  a.J = desc->J;
+  const double J = desc->J;
+  a.beta = M_PI * std::sqrt((J / 2.0) * (J / 2.0) * 1.5 * 1.5 - 0.8);
+  a.inv_i0b = 1.0 / host_i0(a.beta);
+  a.Ky = p->Ky;
+  a.Kx = p->Kx;
+  a.u0 = p->blk_u0[block];
+  a.flag = p->at<int>(p->off_flag) + 2;
+  const int zero = 0;
+  HIP_TRY(hipMemcpyAsync(a.flag, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+  const BlockInfo& bi = p->W().binfo[block];
+  HIP_TRY(launch_build_g(a, bi.item0, bi.item1, s));
+  int bad = 0;
+  HIP_TRY(hipMemcpyAsync(&bad, a.flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (bad) return PHI_ERR_RANGE;
+  p->g_loaded[block] = 1;
+  return PHI_OK;
+}
+
+phi_status phi_plan_read_g(phi_plan p, int64_t block, void* h_windows, int32_t host_type, void* stream) {
+  if (!p) return PHI_ERR_ARG;
+  if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
+  if (host_type != PHI_HOST_C128 && host_type != PHI_HOST_C64) return PHI_ERR_ARG;
+  if (p->gprec == PHI_G_KB || !p->bound || !p->g_loaded[block]) return PHI_ERR_STATE;
+  const int64_t u0 = p->blk_u0[block], n = p->blk_n[block];
+  if (n == 0) return PHI_OK;
+  if (!h_windows) return PHI_ERR_ARG;
+  std::lock_guard<std::mutex> lk(p->mu);
+  hipStream_t s = (hipStream_t)stream;
+  const size_t eb = p->g_elem_bytes();
+  const int64_t t0 = p->tap_off[u0], nt = p->tap_off[u0 + n] - t0;
+  std::vector<unsigned char> raw((size_t)nt * eb);
+  HIP_TRY(hipMemcpyAsync(raw.data(), p->ws + p->off_G + (size_t)t0 * eb, raw.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  std::vector<int64_t> uoff(n + 1, 0);
+  std::vector<int32_t> uS(n);
+  for (int64_t k = 0; k < n; ++k) uS[p->perm[u0 + k] - u0] = p->S_plan[u0 + k];
+  for (int64_t i = 0; i < n; ++i) uoff[i + 1] = uoff[i] + (int64_t)uS[i] * uS[i];
+  parallel_for(n, [&](int64_t lo, int64_t hi) {
+    for (int64_t k = lo; k < hi; ++k) {
+      const int64_t ui = p->perm[u0 + k] - u0, src0 = p->tap_off[u0 + k] - t0;
+      for (int64_t e = 0; e < uoff[ui + 1] - uoff[ui]; ++e) {
+        const unsigned char* r = raw.data() + (size_t)(src0 + e) * eb;
+        double re, im;
+        if (p->gprec == PHI_G_C64) {
+          float f[2];
+          std::memcpy(f, r, 8);
+          re = f[0];
+          im = f[1];
+        } else if (p->gprec == PHI_G_F16) {
+          _Float16 hv[2];
+          std::memcpy(hv, r, 4);
+          re = (double)hv[0];
+          im = (double)hv[1];
+        } else {
+          uint16_t b[2];
+          std::memcpy(b, r, 4);
+          const uint32_t ur = (uint32_t)b[0] << 16, ui2 = (uint32_t)b[1] << 16;
+          float fr, fi;
+          std::memcpy(&fr, &ur, 4);
+          std::memcpy(&fi, &ui2, 4);
+          re = fr;
+          im = fi;
+        }
+        const int64_t d = uoff[ui] + e;
+        if (host_type == PHI_HOST_C128) {
+          static_cast<double*>(h_windows)[2 * d] = re;
+          static_cast<double*>(h_windows)[2 * d + 1] = im;
+        } else {
+          static_cast<float*>(h_windows)[2 * d] = (float)re;
+          static_cast<float*>(h_windows)[2 * d + 1] = (float)im;
+        }
+      }
+    }
+  });
+  return PHI_OK;
+}
+
 }  // extern "C"

@@ -99,6 +99,26 @@ hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, do
 hipError_t launch_permute(const float2* src, float2* dst, const int32_t* perm, int64_t n,
                           int to_plan, hipStream_t s);
 
+// Device G builder (rows from per-visibility tables, FP64)
+struct BuildArgs {
+  const Item* items;
+  const uint32_t* meta;
+  const int32_t* perm;     // plan position -> user index (global)
+  void* G;
+  int gprec;               // 0 c64, 1 f16, 2 bf16
+  const double* kappa;     // [n][2], user order within the block
+  const int32_t* h;        // [n]
+  const double* a;         // [n]
+  const int32_t* ant;      // [n][2] or null
+  const double* dde;       // complex128 [n_ant][sa][sa] as (re, im) pairs, or null
+  int n_ant, sa, J;
+  double beta, inv_i0b;
+  int Ky, Kx;
+  int64_t u0;              // the block's first plan / user position
+  int* flag;               // set to 1 on a row that does not match its declared window
+};
+hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s);
+
 // Zero taps kept behind G: a window's fetch reads 64 * NK taps (NK <= 7)
 // from its first tap, past the window's end.
 constexpr int kGPadTaps = 7 * 64;

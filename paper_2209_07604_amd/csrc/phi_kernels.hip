@@ -1425,6 +1425,170 @@ __global__ __launch_bounds__(64) void k_eps_update(const double* __restrict__ re
   state[3 * b + 2] = count;
 }
 
+// ------------------------------------------------------------- G builder
+// Rows of G from per-visibility tables, in FP64 (definitions with
+// phi_plan_build_g): Kaiser-Bessel taps per axis convolved with the
+// normalised w-chirp, their outer product, then the antenna pair's DDE
+// kernel d_i (*) conj(flip(d_j)).  One wave per work item walks its windows
+// in plan order (tap offsets from the window sizes); the per-window tables
+// live in LDS.  Each tap is rounded once to the stored precision.
+
+// I0 by its power series sum_k ((z/2)^2)^k / (k!)^2 (z <= 30 here: 60 terms
+// leave a tail far below FP64 rounding).
+__device__ __forceinline__ double bessel_i0_series(double z) {
+  const double q = 0.25 * z * z;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k <= 60; ++k) {
+    term *= q / ((double)k * (double)k);
+    sum += term;
+  }
+  return sum;
+}
+
+// d rounded to `sig` significant bits (ties to even), with spacing at least
+// 2^qmin (subnormals of the target); exact in FP64.
+__device__ __forceinline__ double round_sig(double d, int sig, int qmin) {
+  if (!(fabs(d) > 0.0) || !isfinite(d)) return d;
+  int e;
+  (void)frexp(d, &e);
+  const int q = max(e - sig, qmin);
+  return ldexp(rint(ldexp(d, -q)), q);
+}
+
+__device__ __forceinline__ void store_tap(void* G, int gprec, int64_t t, double re, double im) {
+  if (gprec == 0) {
+    reinterpret_cast<float2*>(G)[t] = make_float2((float)re, (float)im);
+  } else if (gprec == 1) {
+    // one rounding FP64 -> FP16 (11 significant bits, subnormal spacing 2^-24);
+    // the rounded value converts exactly
+    const _Float16 hr = (_Float16)(float)round_sig(re, 11, -24);
+    const _Float16 hi = (_Float16)(float)round_sig(im, 11, -24);
+    reinterpret_cast<uint32_t*>(G)[t] =
+        (uint32_t)__builtin_bit_cast(uint16_t, hr) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+  } else {
+    // one rounding FP64 -> BF16 (8 significant bits, subnormal spacing 2^-133)
+    const uint32_t br = __float_as_uint((float)round_sig(re, 8, -133)) >> 16;
+    const uint32_t bi = __float_as_uint((float)round_sig(im, 8, -133)) >> 16;
+    reinterpret_cast<uint32_t*>(G)[t] = br | (bi << 16);
+  }
+}
+
+constexpr int kBuildMaxU = 32;   // J + 2h <= 21 + margin
+constexpr int kBuildMaxSd = 13;  // 2 sa - 1 for sa <= 7
+
+__global__ __launch_bounds__(64) void k_build_g(BuildArgs a, int it0) {
+  __shared__ double psi[2][16];
+  __shared__ double2 cw[kBuildMaxU];
+  __shared__ double2 u[2][kBuildMaxU];
+  __shared__ double2 pk[kBuildMaxSd * kBuildMaxSd];
+  const int lane = threadIdx.x;
+  const Item item = a.items[it0 + blockIdx.x];
+  const int J = a.J;
+  int64_t tap = item.tap0;
+  for (int v = item.v0; v < item.v1; ++v) {
+    const uint32_t m = a.meta[v];
+    const int Sd = 2 * (int)(m >> 26) + 1, byd = m & 8191, bxd = (m >> 13) & 8191;
+    const int64_t uu = (int64_t)a.perm[v] - a.u0;
+    const double ky = a.kappa[2 * uu], kx = a.kappa[2 * uu + 1];
+    const int hh = a.h[uu];
+    const double aa = a.a[uu];
+    const int ai = a.ant ? a.ant[2 * uu] : -1, aj = a.ant ? a.ant[2 * uu + 1] : -1;
+    const bool dde = ai >= 0;
+    const int sd = dde ? 2 * a.sa - 1 : 1;
+    const int Lu = J + 2 * hh, S = Lu + sd - 1, ext = hh + (sd - 1) / 2;
+    const double fy = floor(ky - 0.5 * J), fx = floor(kx - 0.5 * J);
+    bool ok = isfinite(ky) && isfinite(kx) && hh >= 0 && Lu <= kBuildMaxU && S == Sd &&
+              (!dde || (ai < a.n_ant && aj >= 0 && aj < a.n_ant));
+    if (ok) {
+      int64_t by = (int64_t)fy + 1 - ext, bx = (int64_t)fx + 1 - ext;
+      by %= a.Ky;
+      bx %= a.Kx;
+      if (by < 0) by += a.Ky;
+      if (bx < 0) bx += a.Kx;
+      ok = by == byd && bx == bxd;
+    }
+    if (!ok) {
+      if (lane == 0) a.flag[0] = 1;
+      tap += (int64_t)Sd * Sd;
+      continue;
+    }
+    // Kaiser-Bessel taps: lanes 0..J-1 for y, 32..32+J-1 for x
+    if ((lane & 31) < J) {
+      const int i = lane & 31;
+      const double d = (lane < 32 ? ky - (fy + 1.0 + i) : kx - (fx + 1.0 + i)) * (2.0 / J);
+      const double t = 1.0 - d * d;
+      psi[lane >> 5][i] = t >= 0.0 ? bessel_i0_series(a.beta * sqrt(t)) * a.inv_i0b : 0.0;
+    }
+    // w-chirp taps k = -h..h (unnormalised)
+    if (lane <= 2 * hh) {
+      const int k = lane - hh;
+      const double c = cos(M_PI * k / (2.0 * (hh + 1)));
+      const double ph = -M_PI * (double)k * k / (4.0 * fmax(aa, 0.5));
+      cw[lane] = make_double2(c * c * cos(ph), c * c * sin(ph));
+    }
+    __syncthreads();
+    // normalisation (same sum on every lane, fixed order)
+    double2 cs = make_double2(0.0, 0.0);
+    for (int k = 0; k <= 2 * hh; ++k) {
+      cs.x += cw[k].x;
+      cs.y += cw[k].y;
+    }
+    const double cn = cs.x * cs.x + cs.y * cs.y;
+    // u = psi (*) (c / sum c): lanes 0..Lu-1 for y, 32.. for x
+    if ((lane & 31) < Lu) {
+      const int i = lane & 31, ax = lane >> 5;
+      double2 acc = make_double2(0.0, 0.0);
+      for (int j = max(0, i - 2 * hh); j <= min(i, J - 1); ++j) {
+        const double2 c = cw[i - j];
+        acc.x += psi[ax][j] * c.x;
+        acc.y += psi[ax][j] * c.y;
+      }
+      // divide by the (complex) tap sum
+      u[ax][i] = make_double2((acc.x * cs.x + acc.y * cs.y) / cn, (acc.y * cs.x - acc.x * cs.y) / cn);
+    }
+    // pair kernel p[r][c] = sum_{p,q} d_i[p][q] conj(d_j[sa-1-(r-p)][sa-1-(c-q)])
+    if (dde) {
+      const int sa = a.sa;
+      const double2* __restrict__ di = reinterpret_cast<const double2*>(a.dde) + (int64_t)ai * sa * sa;
+      const double2* __restrict__ dj = reinterpret_cast<const double2*>(a.dde) + (int64_t)aj * sa * sa;
+      for (int e = lane; e < sd * sd; e += 64) {
+        const int r = e / sd, c = e - (e / sd) * sd;
+        double2 acc = make_double2(0.0, 0.0);
+        for (int p = max(0, r - sa + 1); p <= min(r, sa - 1); ++p)
+          for (int q = max(0, c - sa + 1); q <= min(c, sa - 1); ++q) {
+            const double2 x = di[p * sa + q], y = dj[(sa - 1 - (r - p)) * sa + (sa - 1 - (c - q))];
+            acc.x += x.x * y.x + x.y * y.y;  // x conj(y)
+            acc.y += x.y * y.x - x.x * y.y;
+          }
+        pk[e] = acc;
+      }
+    }
+    __syncthreads();
+    for (int t = lane; t < S * S; t += 64) {
+      const int r = t / S, c = t - (t / S) * S;
+      double re = 0.0, im = 0.0;
+      if (!dde) {
+        const double2 y = u[0][r], x = u[1][c];
+        re = y.x * x.x - y.y * x.y;
+        im = y.x * x.y + y.y * x.x;
+      } else {
+        for (int p = max(0, r - Lu + 1); p <= min(r, sd - 1); ++p) {
+          const double2 y = u[0][r - p];
+          for (int q = max(0, c - Lu + 1); q <= min(c, sd - 1); ++q) {
+            const double2 x = u[1][c - q], w = pk[p * sd + q];
+            const double yr = y.x * x.x - y.y * x.y, yi = y.x * x.y + y.y * x.x;
+            re += yr * w.x - yi * w.y;
+            im += yr * w.y + yi * w.x;
+          }
+        }
+      }
+      store_tap(a.G, a.gprec, tap + t, re, im);
+    }
+    __syncthreads();  // the tables are rewritten for the next window
+    tap += (int64_t)S * S;
+  }
+}
+
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
 // Threads of a row transform: a row of 4096 or more points fills 32-64 KiB of
@@ -1752,6 +1916,12 @@ hipError_t launch_eps_update(const double* res, const double* var, const BlockIn
   if (nblk <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_eps_update, dim3((nblk + 63) / 64), dim3(64), 0, s, res, var, blocks, nblk, rule, eps,
                      state);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s) {
+  if (it1 <= it0) return hipSuccess;
+  hipLaunchKernelGGL(k_build_g, dim3(it1 - it0), dim3(64), 0, s, a, it0);
   return hipGetLastError();
 }
 

@@ -212,6 +212,37 @@ class Plan:
                                               _stream(torch, self.device)), "phi_power_iteration")
         return nu
 
+    # ------------------------------------------------------------- G builder
+    def build_g(self, block, kappa, h, a, ant=None, dde=None, J=7):
+        """Compute block `block`'s rows of G on the device (phi_plan_build_g).
+        kappa: float64 [n, 2]; h: int32 [n]; a: float64 [n]; ant: int32
+        [n, 2] or None; dde: complex128 [n_ant, sa, sa] or None (device
+        tensors, user order of the block)."""
+        import torch
+        d = L.GBuild()
+        d.J = int(J)
+        d.n_ant = int(dde.shape[0]) if dde is not None else 0
+        d.sa = int(dde.shape[1]) if dde is not None else 1
+        for t, dt in ((kappa, torch.float64), (h, torch.int32), (a, torch.float64)):
+            if t.dtype != dt or not t.is_contiguous():
+                raise ValueError("kappa float64 [n, 2], h int32 [n], a float64 [n], contiguous")
+        if (ant is None) != (dde is None):
+            raise ValueError("ant and dde go together")
+        if ant is not None and (ant.dtype != torch.int32 or dde.dtype != torch.complex128):
+            raise ValueError("ant int32 [n, 2], dde complex128 [n_ant, sa, sa]")
+        L.check(self._lib.phi_plan_build_g(self._h, int(block), ctypes.byref(d), _dptr(kappa), _dptr(h), _dptr(a),
+                                           _dptr(ant), _dptr(dde), _stream(torch, self.device)),
+                "phi_plan_build_g")
+
+    def read_g(self, block, n_taps):
+        """Block `block`'s stored G in user order (complex128, n_taps = sum of
+        its S^2), converted exactly from the stored precision."""
+        import torch
+        out = np.empty(int(n_taps), dtype=np.complex128)
+        L.check(self._lib.phi_plan_read_g(self._h, int(block), _ptr(out), L.HOST_C128,
+                                          _stream(torch, self.device)), "phi_plan_read_g")
+        return out
+
     # ------------------------------------------------------------ PDFB loop
     @staticmethod
     def eps_rule(lambda_lo=0.99, lambda_hi=1.01, lambda_mix=0.618, var_tol=1e-3, min_gap=10, freeze=True):

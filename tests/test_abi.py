@@ -111,6 +111,22 @@ def test_create_null_and_ok():
         assert run(3, ctypes.byref(r)) == -3, bad
         assert lib.phi_eps_update(h, buf[0], buf[1], ctypes.byref(r), buf[2], buf[3], None) == -3, bad
     assert lib.phi_eps_update(h, buf[0], buf[1], None, buf[2], buf[3], None) == -1
+    # G builder: descriptor checks first, then the plan state
+    gb = L.GBuild(7, 0, 1, 0)
+    assert lib.phi_plan_build_g(h, 0, ctypes.byref(gb), buf[0], buf[1], buf[2], None, None, None) == -8
+    assert lib.phi_plan_build_g(h, 7, ctypes.byref(gb), buf[0], buf[1], buf[2], None, None, None) == -3
+    assert lib.phi_plan_build_g(h, 0, None, buf[0], buf[1], buf[2], None, None, None) == -1
+    assert lib.phi_plan_build_g(None, 0, ctypes.byref(gb), buf[0], buf[1], buf[2], None, None, None) == -1
+    for J in (2, 4, 13):
+        assert lib.phi_plan_build_g(h, 0, ctypes.byref(L.GBuild(J, 0, 1, 0)), buf[0], buf[1], buf[2],
+                                    None, None, None) == -3
+    assert lib.phi_plan_build_g(h, 0, ctypes.byref(gb), buf[0], buf[1], buf[2], buf[3], None, None) == -1
+    for n_ant, sa in ((0, 3), (4, 2), (4, 9)):
+        assert lib.phi_plan_build_g(h, 0, ctypes.byref(L.GBuild(7, n_ant, sa, 0)), buf[0], buf[1], buf[2],
+                                    buf[3], buf[4], None) == -3
+    assert lib.phi_plan_read_g(h, 0, buf[0], 0, None) == -8
+    assert lib.phi_plan_read_g(h, 0, buf[0], 5, None) == -1
+    assert lib.phi_plan_read_g(h, 9, buf[0], 0, None) == -3
     assert lib.phi_pdfb_primal(None, buf[0], buf[1], buf[2], buf[3], None, None) == -1
     assert lib.phi_power_iteration(None, None, None, 3, None, None) == -1
     assert lib.phi_plan_bind(h, None, n.value, None) == -1
