@@ -69,16 +69,23 @@ def generate(name, log_every=8, channels=0, windows=True):
                                   n_vis=[prob.n_vis[l] for l in sel],
                                   nu=None if prob.nu is None else prob.nu[sel])
     t0 = time.time()
-    blocks, kappas = [], []
+    blocks, kappas, wtab = [], [], []
     K = np.array([prob.Ky, prob.Kx], dtype=np.float64)
     for k, (l, b) in enumerate(prob.block_list()):
         blk = prob.block(l, b)
         w = blk.windows(np.complex64)[0] if windows else None
         blocks.append((blk.base, blk.S, w))
         kappas.append(blk.omega * K / (2 * np.pi))
+        # the generator's w-kernel tables (half-width h, chirp parameter a)
+        # for rows without DDE, as the device G builder takes them
+        if not prob.dde:
+            h = ((blk._skw - 7) // 2).astype(np.int32)
+            a = prob.w_max_cells * blk.w
+            wtab.append((h, np.where(np.round(a) > h, h.astype(np.float64), a)))
         if k % log_every == 0:
             log("[bench] generated block %d/%d (%.0f s)" % (k + 1, len(prob.block_list()), time.time() - t0))
-    return prob, blocks, kappas
+    generate.seconds = time.time() - t0
+    return prob, blocks, kappas, wtab
 
 
 def cpu_baseline(prob, plan, theta, budget_s=30.0):
@@ -148,23 +155,19 @@ def _event_ms(fn, n):
     return e0.elapsed_time(e1) / n
 
 
-def stream_rates(dev, mib=2048):
-    """Practical streaming bounds on this GPU, from plain library kernels on
-    a 2 GiB buffer: device copy (read + write bytes / time) and a full sum
-    (bytes read / time)."""
+def stream_copy_gbs(dev, mib=2048):
+    """Device-to-device copy rate (read + write bytes / time) of a plain
+    library copy of a 2 GiB buffer: a practical streaming bound on this GPU."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    acc = torch.empty((), dtype=torch.float32, device=dev)
     for _ in range(3):
         dst.copy_(src)
-        torch.sum(src, dim=0, out=acc)
     torch.cuda.synchronize()
-    copy_ms = _event_ms(lambda: dst.copy_(src), 10)
-    read_ms = _event_ms(lambda: torch.sum(src, dim=0, out=acc), 10)
+    ms = _event_ms(lambda: dst.copy_(src), 10)
     del src, dst
-    return 2.0 * n * 4 / (copy_ms * 1e-3) / 1e9, n * 4 / (read_ms * 1e-3) / 1e9
+    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
 
 
 def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
@@ -213,6 +216,38 @@ def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
                    "rule": "adaptive l2 bounds (lambda 0.99/1.01/0.618, var_tol 1e-3, min_gap 10)",
                    "steps": "sigma_b = 1/||Phi_l||^2 (10 power steps), tau_l = 0.9"}
     return out
+
+
+def time_gbuild(p, kappas, wtab, xt, v0, y, eps, dev):
+    """Rebuild every block's G on the device (phi_plan_build_g) from the
+    generator's tables, timed on the wall clock (each call is synchronous),
+    then one dual step on the rebuilt G against the step on the host-loaded
+    G (same inputs)."""
+    import torch
+    v = v0.clone()
+    grad0, _, _ = p.dual_step(xt, v, y, eps)
+    vp0, grad0 = v.clone(), grad0.clone()
+    tabs = [(torch.from_numpy(np.ascontiguousarray(k)).to(dev), torch.from_numpy(h).to(dev),
+             torch.from_numpy(np.ascontiguousarray(a)).to(dev)) for k, (h, a) in zip(kappas, wtab)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b, (k, h, a) in enumerate(tabs):
+        p.build_g(b, k, h, a, J=7)
+    ms = (time.perf_counter() - t0) * 1e3
+    v = v0.clone()
+    grad1, _, _ = p.dual_step(xt, v, y, eps)
+    torch.cuda.synchronize()
+    rel = lambda a_, b_: float(torch.linalg.vector_norm((a_ - b_).to(torch.complex128)) /
+                               torch.linalg.vector_norm(b_.to(torch.complex128)))
+    info = p.info()
+    return {"ms": ms, "taps": int(info["n_taps"]), "G_bytes": int(info["g_bytes"]),
+            "G_GB_per_s_written": info["g_bytes"] / (ms * 1e-3) / 1e9,
+            "host_generation_s": generate.seconds,
+            "dual_step_rel_diff_vs_host_G": {"v_plus": rel(v, vp0), "grad": rel(grad1, grad0)},
+            "note": "FP64 rows (Kaiser-Bessel taps (*) w-chirp) rounded once to the stored precision; wall "
+                    "clock of one synchronous call per block; host_generation_s is the seeded generator "
+                    "building the same windows on the host; the host-loaded G came from complex64 windows "
+                    "(rounded twice), hence the small step difference"}
 
 
 def run_dr(args, prob, blocks, theta, y_user, starts, s_y, s_x, results, dev):
@@ -285,6 +320,7 @@ def main():
     ap.add_argument("--channels", type=int, default=0, help="use this many channels of the configuration")
     ap.add_argument("--dr", action="store_true",
                     help="also time the visibility-gridding reduced step (Section 3.4) on the same data")
+    ap.add_argument("--no-gbuild", action="store_true", help="skip timing the device G builder")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -299,8 +335,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     forms = [f for f in args.forms.split(",") if f]
-    prob, blocks, kappas = generate(args.config, channels=args.channels,
-                                    windows=args.dr or any(not f.endswith("_kb") for f in forms))
+    prob, blocks, kappas, wtab = generate(args.config, channels=args.channels,
+                                          windows=args.dr or any(not f.endswith("_kb") for f in forms))
     L = prob.L
     n_vis = [len(s) for (_, s, _) in blocks]
     base = np.concatenate([b for (b, _, _) in blocks])
@@ -321,7 +357,6 @@ def main():
         log("[bench] plan %s ready (%.0f s), info %s" % (prec, time.time() - t0, p.info()))
     if not args.dr:
         del blocks
-    del kappas
 
     # inputs: x~ = x/2, y = theta Phi0 x + n at 30 dB (theta from the c64 form), v ~ 0.1 CN
     gen = torch.Generator(device=dev)
@@ -414,6 +449,12 @@ def main():
         log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
             form, ms, M / (ms * 1e-3), {k_: round(v_ / max(calls, 1), 3) for k_, v_ in stages.items()}))
 
+    line_gb = None
+    if wtab and not args.no_gbuild and "batched_f16" in results:
+        log("[bench] device G builder")
+        line_gb = time_gbuild(plans["f16"], kappas, wtab, xt, plans["f16"].to_plan(v_init), y_plan["f16"], eps, dev)
+        log("[bench] G builder: %s" % line_gb)
+    del kappas
     if args.dr:
         line_dr = run_dr(args, prob, blocks, theta, (th_vis * pref.from_plan(y0) + noise).cpu().numpy(),
                          starts, s_y, s_x, results, dev)
@@ -433,8 +474,8 @@ def main():
     extras = time_extras(hp, x, xt, hp.to_plan(v_init), y_plan[head.split("_")[1]], eps, args.steps, args.warmup,
                          dev)
     # (not in counter runs: their only large copy must be the calibration copy)
-    copy_gbs, read_gbs = (None, None) if args.calib_copy_mib else stream_rates(dev)
-    log("[bench] extras %s, stream copy %s GB/s, read %s GB/s" % (extras, copy_gbs, read_gbs))
+    copy_gbs = None if args.calib_copy_mib else stream_copy_gbs(dev)
+    log("[bench] extras %s, stream copy %s GB/s" % (extras, copy_gbs))
     if "batched_kb" in results and "batched_f16" in results:
         results["batched_kb"]["speedup_vs_batched_f16"] = (results["batched_f16"]["ms_per_step"] /
                                                            results["batched_kb"]["ms_per_step"])
@@ -468,8 +509,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs, "stream_read_GBs": read_gbs,
-                     "frac_of_stream_read": achieved / read_gbs if read_gbs else None},
+                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs,
+                     "frac_of_stream_copy": achieved / copy_gbs if copy_gbs else None},
         "forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
         "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
@@ -478,6 +519,8 @@ def main():
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
     if args.dr:
         line["dimensionality_reduction"] = line_dr
+    if line_gb:
+        line["g_builder"] = line_gb
     if not args.no_cpu_baseline:
         line["cpu_baseline"], line["err_vs_fp64_" + head] = cpu_baseline(prob, hp, theta)
     print(json.dumps(line), flush=True)
