@@ -1597,6 +1597,11 @@ template <int N>
 constexpr int row_threads() {
   return N >= 4096 ? 512 : kFftThreads;
 }
+// Column panels of 32 KiB or more likewise get 512 threads, 64 KiB ones 1024.
+template <int CELLS>
+constexpr int panel_threads() {
+  return CELLS * 8 >= 65536 ? 1024 : CELLS * 8 >= 32768 ? 512 : kFftThreads;
+}
 constexpr int kFftCells = 8192;  // N * W per work-group: 64 KiB of LDS
 
 template <int N>
@@ -1622,8 +1627,17 @@ template <int N>
 constexpr int col_split1() {
   return N == 3072 ? 48 : N == 4096 ? 64 : N == 5120 ? 40 : N == 6144 ? 48 : N == 8192 ? 64 : 0;
 }
-constexpr int kColW2 = 32;  // columns per work-group in the two-pass transform (divides
-                            // every valid Kx: image edges are multiples of 16)
+// Columns per work-group in the two-pass transform (divides every valid Kx:
+// image edges are multiples of 16, so Kx is a multiple of 32; 64-column
+// panels in the second pass measured slower).
+constexpr int kColW2 = 32;
+
+template <int N1, int N2, bool INV>
+hipError_t colfft2_pass_b(float2* grid, const float2* tw, int Kx, int l0, int nl, hipStream_t s) {
+  constexpr int W = kColW2, T = panel_threads<N1 * W>();
+  hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, T, INV>), dim3(N2 * (Kx / W), nl), dim3(T), 0, s, grid, tw, Kx, l0);
+  return hipGetLastError();
+}
 
 template <int N>
 hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int Ny, int Kx, int l0, int nl,
@@ -1632,16 +1646,16 @@ hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int 
   if constexpr (N1 > 0) {
     constexpr int N2 = N / N1, W = kColW2;
     if (Kx % W == 0) {
-      hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, kFftThreads>), dim3(N1 * (Kx / W), nl), dim3(kFftThreads), 0, s,
-                         half, grid, tw, Ny, Kx, l0);
-      hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, kFftThreads, false>), dim3(N2 * (Kx / W), nl), dim3(kFftThreads),
-                         0, s, grid, tw, Kx, l0);
-      return hipGetLastError();
+      constexpr int TA = panel_threads<N2 * W>();
+      hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, half, grid, tw,
+                         Ny, Kx, l0);
+      return colfft2_pass_b<N1, N2, false>(grid, tw, Kx, l0, nl, s);
     }
   }
   constexpr int W = col_width<N>();
   if (Kx % W) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_colfft_fwd<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, half, grid,
+  constexpr int NT = panel_threads<N * W>();
+  hipLaunchKernelGGL((k_colfft_fwd<N, W, NT>), dim3(Kx / W, nl), dim3(NT), 0, s, half, grid,
                      tw, Ny, Kx, l0);
   return hipGetLastError();
 }
@@ -1654,16 +1668,18 @@ hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int 
     if (Kx % W == 0) {
       // the pass along k1 runs in place on the grid, which the adjoint no
       // longer needs afterwards
-      hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, kFftThreads, true>), dim3(N2 * (Kx / W), nl), dim3(kFftThreads), 0,
-                         s, const_cast<float2*>(grid), tw, Kx, l0);
-      hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, kFftThreads>), dim3(N1 * (Kx / W), nl), dim3(kFftThreads), 0, s,
-                         grid, half, tw, Ny, Kx, l0);
+      constexpr int TA = panel_threads<N2 * W>();
+      const hipError_t e = colfft2_pass_b<N1, N2, true>(const_cast<float2*>(grid), tw, Kx, l0, nl, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, grid, half, tw,
+                         Ny, Kx, l0);
       return hipGetLastError();
     }
   }
   constexpr int W = col_width<N>();
   if (Kx % W) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_colfft_inv<N, W, kFftThreads>), dim3(Kx / W, nl), dim3(kFftThreads), 0, s, grid, half,
+  constexpr int NT = panel_threads<N * W>();
+  hipLaunchKernelGGL((k_colfft_inv<N, W, NT>), dim3(Kx / W, nl), dim3(NT), 0, s, grid, half,
                      tw, Ny, Kx, l0);
   return hipGetLastError();
 }
