@@ -321,6 +321,8 @@ def main():
     ap.add_argument("--dr", action="store_true",
                     help="also time the visibility-gridding reduced step (Section 3.4) on the same data")
     ap.add_argument("--no-gbuild", action="store_true", help="skip timing the device G builder")
+    ap.add_argument("--device-g", action="store_true",
+                    help="build G on the device from the generator's tables (no host windows)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -335,8 +337,15 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     forms = [f for f in args.forms.split(",") if f]
+    if args.device_g and args.dr:
+        print("--device-g and --dr are exclusive (the reduction needs host windows)", file=sys.stderr)
+        sys.exit(2)
     prob, blocks, kappas, wtab = generate(args.config, channels=args.channels,
-                                          windows=args.dr or any(not f.endswith("_kb") for f in forms))
+                                          windows=not args.device_g and
+                                          (args.dr or any(not f.endswith("_kb") for f in forms)))
+    if args.device_g and not wtab:
+        print("--device-g needs a workload without DDE", file=sys.stderr)
+        sys.exit(2)
     L = prob.L
     n_vis = [len(s) for (_, s, _) in blocks]
     base = np.concatenate([b for (b, _, _) in blocks])
@@ -351,6 +360,10 @@ def main():
         for k, (_, _, w) in enumerate(blocks):
             if prec == "kb":
                 p.load_kb(k, kappas[k])   # taps evaluated in the kernels
+            elif args.device_g:           # rows computed on the device from the generator's tables
+                p.build_g(k, torch.from_numpy(np.ascontiguousarray(kappas[k])).to(dev),
+                          torch.from_numpy(wtab[k][0]).to(dev),
+                          torch.from_numpy(np.ascontiguousarray(wtab[k][1])).to(dev), J=7)
             else:
                 p.load_g(k, w)
         plans[prec] = p
@@ -503,6 +516,7 @@ def main():
                                "w-stencils %d..%d, 30 dB" % (args.config, L, sorted(set(prob.n_blocks)),
                                                               prob.Ny, prob.Nx, prob.Ky, prob.Kx, M,
                                                               int(S.min()), int(S.max())),
+                   "g_source": "device builder" if args.device_g else "host windows",
                    "form": head.replace("_", " ") + " (hipGraph)", "g_storage": head.split("_")[1],
                    "taps": int(info["n_taps"])},
         "hbm_alg_GBs": r["alg_GBs"],
