@@ -11,7 +11,8 @@ data.  Forms timed on the same data: plain FP32 (complex64 G, every stage
 launched per channel), batched FP32, batched FP16-G (the headline), batched
 BF16-G; batched forms replay a hipGraph.  On direction-independent workloads
 (one window size) the form batched_kb evaluates the Kaiser-Bessel taps in the
-kernels instead of reading stored G.
+kernels instead of reading stored G; fused_<prec> runs the dual step in one
+pass over G (PHI_FUSED_GH).
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -332,7 +333,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT
+    from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
@@ -417,13 +418,16 @@ def main():
         grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
         rho = torch.empty(nblk, dtype=torch.float64, device=dev)
         res = torch.empty(nblk, dtype=torch.float64, device=dev)
-        if kind == "batched" and args.tile:
+        if kind in ("batched", "fused") and args.tile:
             p.set_tuning(args.tile, args.persist)
-        elif kind == "batched" and not args.no_autotune:
+        elif kind in ("batched", "fused") and not args.no_autotune:
             rc = p.autotune(3)
             log("[bench] autotune %s -> rc %d, tile %d, persist %d" % (
                 prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
-        flags_now = p.info()["persist_blocks"] and PERSISTENT
+        # the autotuner may have chosen the one-pass dual step (info "fused");
+        # fused_<prec> forces it, plain_<prec> never uses it
+        fused = kind == "fused" or (kind == "batched" and bool(p.info()["fused"]))
+        flags_now = (p.info()["persist_blocks"] and PERSISTENT) | (FUSED_GH if fused else 0)
         p.set_flags((PER_CHANNEL if kind == "plain" else GRAPH) | flags_now)
         log("[bench] %s: warm-up" % form)
         for _ in range(args.warmup):
@@ -494,10 +498,12 @@ def main():
                                                            results["batched_kb"]["ms_per_step"])
     r = results[head]
     info = r["info"]
-    gather_ms, scatter_ms = r["stage_ms"]["gather"], r["stage_ms"]["scatter"]
-    dom = "gather" if gather_ms >= scatter_ms else "scatter"
-    alg = info["alg_bytes_gather"] if dom == "gather" else info["alg_bytes_scatter"]
-    dur = (gather_ms if dom == "gather" else scatter_ms) * 1e-3
+    # dominant G kernel: gather, scatter, or the fused pass (which moves the
+    # gather's algorithmic bytes: G once, metadata, v and y in, c out)
+    cand = {k_: r["stage_ms"].get(k_, 0.0) for k_ in ("gather", "scatter", "dual_gs")}
+    dom = max(cand, key=cand.get)
+    alg = info["alg_bytes_scatter"] if dom == "scatter" else info["alg_bytes_gather"]
+    dur = cand[dom] * 1e-3
     achieved = alg / dur / 1e9
     line = {
         "metric": METRIC,

@@ -95,7 +95,13 @@ enum {
   PHI_PER_CHANNEL = 1,  /* launch every stage per channel (the plain form)
                            instead of one launch over all channels/blocks  */
   PHI_GRAPH = 2,        /* replay the dual step from a captured hipGraph    */
-  PHI_PERSISTENT = 4    /* G stages run as a persistent grid over work items */
+  PHI_PERSISTENT = 4,   /* G stages run as a persistent grid over work items */
+  PHI_FUSED_GH = 8      /* dual step in one pass over G (c and G^H theta c
+                           from the same taps; sigma * scale applied to v+
+                           and in the merge) instead of a G pass and a G^H
+                           pass; used with stored G where the item's grid
+                           tile and one accumulator per wave fit a
+                           work-group's LDS (e.g. 16-cell tiles)            */
 };
 
 typedef struct {
@@ -133,7 +139,8 @@ typedef struct {
   int32_t ky, kx, tile, n_stages;
   int32_t persist_blocks;      /* persistent G-stage grid in use (0 = one
                                   work-group per item)                       */
-  int32_t reserved;
+  int32_t fused;               /* 1 if the dual step runs in one pass over G
+                                  (PHI_FUSED_GH set and usable)              */
 } phi_info;
 
 /* Validate `desc`, sort visibilities and build the work lists (host only,
@@ -272,7 +279,9 @@ phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
  * G-stage launch shapes (one work-group per item, or a persistent grid of 4
  * work-groups per compute unit) on the bound plan with its loaded G: `reps`
  * rounds of gather + scatter + merge on scratch vectors inside the
- * workspace.  Keeps the fastest; overwrites the grid buffers.  Synchronous. */
+ * workspace.  Keeps the fastest; then, with stored G where it fits, times
+ * the one-pass dual step against the two passes and sets or clears
+ * PHI_FUSED_GH accordingly.  Overwrites the grid buffers.  Synchronous. */
 phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
 
 /* ---------------------------------------------------------------------------

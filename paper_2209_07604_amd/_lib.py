@@ -17,7 +17,7 @@ STATUS = {
 }
 G_PREC = {"c64": 0, "f16": 1, "bf16": 2, "kb": 3}
 HOST_C128, HOST_C64 = 0, 1
-PER_CHANNEL, GRAPH, PERSISTENT = 1, 2, 4
+PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH = 1, 2, 4, 8
 
 # every symbol include/phi.h declares
 EXPORTS = [
@@ -58,7 +58,7 @@ class Info(ctypes.Structure):
         ("alg_bytes_gather", ctypes.c_double), ("alg_bytes_scatter", ctypes.c_double),
         ("ky", ctypes.c_int32), ("kx", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("fused", ctypes.c_int32),
     ]
 
 

@@ -83,9 +83,9 @@ struct StageTimer {
   }
 };
 
-const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather",     "finalize",  "scatter",
-                             "merge",      "colfft_inv", "rowfft_inv", "pdfb_primal", "eps_update"};
-constexpr int kNumStages = 10;
+const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather",      "finalize",   "scatter", "merge",
+                             "colfft_inv", "rowfft_inv", "pdfb_primal", "eps_update", "dual_gs", "vscale"};
+constexpr int kNumStages = 12;
 
 }  // namespace
 
@@ -138,6 +138,8 @@ struct phi_plan_s {
   // G store bytes per tap (none in the Kaiser-Bessel mode, where taps are
   // evaluated in the kernels from per-visibility fractional coordinates)
   size_t g_elem_bytes() const { return gprec == PHI_G_KB ? 0 : gprec == PHI_G_C64 ? 8 : 4; }
+  // the dual step reads each G tap once (gather and G^H in one pass)
+  bool fused() const;
   int kb_J = 0;                 // window width of the Kaiser-Bessel mode
   double kb_beta = 0.0, kb_inv_i0b = 0.0;
   template <typename T_>
@@ -152,7 +154,7 @@ static phi_status validate(const phi_desc* d) {
   if (d->ny > 4096 || d->nx > 4096) return PHI_ERR_UNSUPPORTED;
   if (!fft_length_supported(2 * d->ny) || !fft_length_supported(2 * d->nx)) return PHI_ERR_UNSUPPORTED;
   if (d->g_prec < PHI_G_C64 || d->g_prec > PHI_G_KB) return PHI_ERR_ARG;
-  if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)) return PHI_ERR_ARG;
+  if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH)) return PHI_ERR_ARG;
   if (d->persist_blocks < 0) return PHI_ERR_ARG;
   const int T = d->tile ? d->tile : 32;
   if (T != 16 && T != 32 && T != 64) return PHI_ERR_ARG;
@@ -307,10 +309,15 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
     TileEntry e{};
     e.poff = it.poff;
     e.pitch = it.pitch;
+    e.blk = it.blk;
     w.entries[fill[t]++] = e;
   }
   w.halo = (p->smax - 1 + T - 1) / T;
   if (w.halo < 1) w.halo = 1;
+}
+
+bool phi_plan_s::fused() const {
+  return gprec != PHI_G_KB && (flags & PHI_FUSED_GH) && fused_lds_bytes(W().max_pitch) > 0;
 }
 
 static void layout(phi_plan_s* p) {
@@ -528,11 +535,15 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->alg_bytes_gather = p->ntaps * bG + p->M * (4.0 + bV + 24.0) + p->L * 8.0 * K;
   info->alg_bytes_scatter = p->ntaps * bG + p->M * (4.0 + bV + 16.0);
   info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * (48.0 + 2.0 * bV) + p->L * (48.0 * K + 8.0 * N);
+  // fused dual step: G read once; the fused pass moves the gather's bytes,
+  // then c is read and v+ written (16 B per visibility)
+  if (p->fused()) info->alg_bytes_dual_step = p->ntaps * bG + p->M * 44.0 + p->L * (48.0 * K + 8.0 * N);
   info->ky = p->Ky;
   info->kx = p->Kx;
   info->tile = p->W().T;
   info->n_stages = kNumStages;
   info->persist_blocks = (p->flags & PHI_PERSISTENT) ? p->persist : 0;
+  info->fused = p->fused() ? 1 : 0;
   return PHI_OK;
 }
 
@@ -778,6 +789,7 @@ struct Runner {
     a.kb_J = p->kb_J;
     a.kb_beta = (float)p->kb_beta;
     a.kb_inv_i0b = (float)p->kb_inv_i0b;
+    a.partials = p->at<float2>(p->off_part);
     return a;
   }
   int persist_blocks() const {
@@ -814,11 +826,13 @@ struct Runner {
                                p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);
     });
   }
-  void adj_fft(float* x, int l0, int l1) {
+  // msig / mscale: per-block merge factors after the fused dual step (null: 1)
+  void adj_fft(float* x, int l0, int l1, const double* msig = nullptr, const double* mscale = nullptr) {
     const int nl = l1 - l0;
     stage(5, [&] {
       return launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, l0, nl, s);
+                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, l0, nl, msig, mscale,
+                          s);
     });
     stage(6, [&] {
       return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
@@ -853,6 +867,22 @@ struct Runner {
     a.sigma = sigma;
     const int it0 = p->W().chan_item0[l0], it1 = p->W().chan_item0[l1];
     const int b0 = p->chan_blk0[l0], b1 = p->chan_blk0[l1];
+    if (p->fused()) {
+      // c and G^H theta c in one pass over G; the per-block factor
+      // sigma * scale goes into v+ and the merge once the norms are known
+      stage(10, [&] {
+        return launch_gather(p->gprec, 2, a, v, y, p->at<double>(p->off_norms), p->W().max_pitch, it0, it1,
+                             persist_blocks(), s);
+      });
+      stage(3, [&] {
+        return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),
+                               p->at<double>(p->off_bpart), eps, rho, res, p->at<double>(p->off_scale),
+                               p->at<int>(p->off_flag), b0, b1 - b0, s);
+      });
+      stage(11, [&] { return launch_vscale(a.items, v, sigma, p->at<double>(p->off_scale), it0, it1, s); });
+      adj_fft(grad, l0, l1, sigma, p->at<double>(p->off_scale));
+      return;
+    }
     stage(2, [&] {
       return launch_gather(p->gprec, 1, a, v, y, p->at<double>(p->off_norms), p->W().max_pitch, it0, it1,
                            persist_blocks(), s);
@@ -978,7 +1008,7 @@ phi_status phi_plan_check(phi_plan p, void* stream) {
 
 phi_status phi_plan_set_flags(phi_plan p, int32_t flags) {
   if (!p) return PHI_ERR_ARG;
-  if (flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT)) return PHI_ERR_ARG;
+  if (flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH)) return PHI_ERR_ARG;
   std::lock_guard<std::mutex> lk(p->mu);
   p->flags = flags;
   if (p->gexec) {
@@ -1059,19 +1089,25 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
   const int saved_flags = p->flags, saved_persist = p->persist;
   float2* vs = p->at<float2>(p->off_vscr);
   // time `reps` rounds of the selected G stages with the current settings
-  auto time_stages = [&](bool g, bool sc, double& ms_out) -> bool {
+  // (fused: the one-pass dual-step kernel instead of the two passes, on the
+  // scratch visibilities as both v and y; the values it writes are unused)
+  auto time_stages = [&](bool g, bool sc, double& ms_out, bool fused = false) -> bool {
     Runner r{p, s, false};
     auto once = [&] {
       const GArgs a = r.gargs();
       const int n = (int)p->W().items.size();
-      if (g && r.err == hipSuccess)
+      if (fused && r.err == hipSuccess)
+        r.err = launch_gather(p->gprec, 2, a, vs, vs, p->at<double>(p->off_norms), p->W().max_pitch, 0, n,
+                              r.persist_blocks(), s);
+      if (!fused && g && r.err == hipSuccess)
         r.err = launch_gather(p->gprec, 0, a, vs, nullptr, nullptr, p->W().max_pitch, 0, n, r.persist_blocks(), s);
-      if (sc && r.err == hipSuccess)
+      if (!fused && sc && r.err == hipSuccess)
         r.err = launch_scatter(p->gprec, 0, a, vs, p->at<float2>(p->off_part), p->W().max_pitch, 0,
                                n, r.persist_blocks(), s);
-      if (sc && r.err == hipSuccess)
+      if ((sc || fused) && r.err == hipSuccess)
         r.err = launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                             p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, 0, p->L, s);
+                             p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, 0, p->L, nullptr,
+                             nullptr, s);
     };
     once();
     (void)hipEventRecord(e0, s);
@@ -1112,6 +1148,16 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
   p->persist = best_p ? best_p : saved_persist;
   p->flags = best_p ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT);
   if (rc == PHI_OK && upload_worklist(p, s) != hipSuccess) rc = PHI_ERR_HIP;
+  // 2) with that tile and shape: the dual step in one pass over G, or two
+  p->flags &= ~PHI_FUSED_GH;
+  if (rc == PHI_OK && p->gprec != PHI_G_KB && fused_lds_bytes(p->W().max_pitch) > 0) {
+    double ms_two = 0, ms_one = 0;
+    if (!time_stages(true, true, ms_two) || !time_stages(false, false, ms_one, true)) {
+      rc = PHI_ERR_HIP;
+    } else if (ms_one < ms_two) {
+      p->flags |= PHI_FUSED_GH;
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;

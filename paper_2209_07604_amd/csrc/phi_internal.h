@@ -45,7 +45,7 @@ constexpr int kGatherWaves = PHI_GATHER_WAVES;
 struct TileEntry {
   int64_t poff;
   int32_t pitch;
-  int32_t pad;
+  int32_t blk;  // block of the item (its merge factor in the fused dual step)
 };
 
 struct BlockInfo {
@@ -71,6 +71,7 @@ struct GArgs {
   const float2* frac;
   int kb_J;
   float kb_beta, kb_inv_i0b;
+  float2* partials;         // per-item tile partials (written by the fused dual step)
 };
 
 // Kernel launchers (phi_kernels.hip).  All asynchronous on `s`.
@@ -86,12 +87,22 @@ hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* 
 // mode: 0 forward (write y), 1 residual (c = v/sigma + phi - y into v; norms)
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y,
                          double* item_norms, int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
+// Fused dual step (mode 2 of the gather): c per visibility and, with the same
+// G taps, G^H theta c into per-item tile partials; the per-block factor
+// sigma * scale is applied by the merge and by launch_vscale.  LDS bytes it
+// needs for the largest pitch; 0 if it does not fit a work-group.
+size_t fused_lds_bytes(int max_pitch);
+// v <- sigma_b * scale_b * v over the visibilities of items [it0, it1)
+hipError_t launch_vscale(const Item* items, float2* vis, const double* sigma, const double* scale, int it0, int it1,
+                         hipStream_t s);
 // mode: 0 adjoint (read v), 1 dual (v+ = sigma*scale*c, written back)
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
                           int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
+// sigma/scale: per-block factors sigma_b * scale_b applied to each item's
+// partial (entry .blk), or scale null for factor 1
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,
                         const TileEntry* entries, int Ky, int Kx, int T, int halo, int l0, int nl,
-                        hipStream_t s);
+                        const double* sigma, const double* scale, hipStream_t s);
 // block_part: [nblk][kFinChunks][2] scratch
 constexpr int kFinChunks = 64;
 hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, double* block_part, const double* eps,

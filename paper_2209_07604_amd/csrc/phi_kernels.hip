@@ -568,16 +568,22 @@ struct Depth {
   static constexpr int value = (regs / NK) < 2 ? 2 : regs / NK;
 };
 
+// MODE 0: y = Phi x.  MODE 1: c = v / sigma + Phi x - y with FP64 norms.
+// MODE 2: as MODE 1, and each window's c is also added as conj(g) theta c
+// into this wave's LDS accumulator (byte offset ab, pitch P, a spare cell per
+// lane behind it) with the same G taps: the dual step's G^H without reading G
+// again (the per-block factor sigma * scale comes later, in the merge).
 template <int GP, int MODE, int NK, int D>
 __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
                                             float2* __restrict__ vis, const float2* __restrict__ yv,
-                                            double& rho2, double& res2, const float2* __restrict__ tile) {
+                                            double& rho2, double& res2, const float2* __restrict__ tile,
+                                            uint32_t ab = 0) {
   using R = typename GRaw<GP>::T;
   const int lane = threadIdx.x & 63;
   const int vlast = v1 - 1, P = item.pitch;
   const float th = a.theta[item.blk];
   float inv_sig = 1.f;
-  if (MODE == 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
+  if (MODE >= 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
   // 64-visibility chunks held one value per lane: metadata of chunks cb and
   // cb + 64 (read per window) with cb + 128 in flight; v and y of chunk cb
   // (read at its flush) with cb + 64 in flight.  Per-window code only reads
@@ -589,7 +595,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
   uint32_t mstg = a.meta[min(cb + 128 + lane, vlast)];
   float2 vc = make_float2(0.f, 0.f), yc = vc, vstg = vc, ystg = vc;
-  if (MODE == 1) {
+  if (MODE >= 1) {
     vc = vis[min(cb + lane, vlast)];
     yc = yv[min(cb + lane, vlast)];
     vstg = vis[min(cb + 64 + lane, vlast)];
@@ -606,7 +612,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       if (MODE == 0) {
         vis[cb + lane] = make_float2(px, py);
       } else {
-        const float2 c = make_float2(vc.x * inv_sig + px - yc.x, vc.y * inv_sig + py - yc.y);
+        const float2 c = make_float2(__builtin_fmaf(vc.x, inv_sig, px) - yc.x, __builtin_fmaf(vc.y, inv_sig, py) - yc.y);
         vis[cb + lane] = c;
         const double rx = (double)px - (double)yc.x, ry = (double)py - (double)yc.y;
         rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
@@ -621,7 +627,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       mcur = mnxt;
       mnxt = mstg;
       mstg = a.meta[min(cb + 128 + lane, vlast)];
-      if (MODE == 1) {
+      if (MODE >= 1) {
         vc = vstg;
         yc = ystg;
         vstg = vis[min(cb + 64 + lane, vlast)];
@@ -658,15 +664,51 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     res.x = me ? px : res.x;
     res.y = me ? py : res.y;
   };
+  // MODE 2: c of window i from its sum (the same operations as the flush, so
+  // the c added here is the c written to v), then conj(g) theta c into the
+  // accumulator: read the window's cells, add, write (distinct cells)
+  auto cval = [&](int i, float sx, float sy) {
+    const float px = th * sx, py = th * sy;
+    const float vx = readlane_f(vc.x, i - cb), vy = readlane_f(vc.y, i - cb);
+    const float yx = readlane_f(yc.x, i - cb), yy = readlane_f(yc.y, i - cb);
+    return make_float2(__builtin_fmaf(vx, inv_sig, px) - yx, __builtin_fmaf(vy, inv_sig, py) - yy);
+  };
+  const uint32_t apark = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
+  auto scatter = [&](const R(&g)[NK], uint32_t mt, float2 c) {
+    const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+    const int S2 = S * S;
+    if (S != lay.S) lay.set(S, P, lane);
+    const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+    const float vx = th * c.x, vy = th * c.y;
+    float2 cur[NK];
+#pragma unroll
+    for (int k = 0; k < NK; ++k)
+      if (k * 64 < S2) cur[k] = lds_load(lay.addr(base_b, k, apark));
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      if (k * 64 < S2) {
+        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+        cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
+        cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
+        cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
+        cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
+        lds_store(lay.addr(base_b, k, apark), cur[k]);
+      }
+    }
+  };
 #pragma unroll
   for (int d = 0; d < D; ++d) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
   auto single = [&](int d, int i) {
     advance(i);
     float ax, ay;
     partial(gb[d], ms[d], ax, ay);
-    gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+    if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
     const float2 s = lane_sum1(ax, ay);
     place(i, s.x, s.y);
+    if (MODE == 2) {
+      scatter(gb[d], ms[d], cval(i, s.x, s.y));
+      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+    }
   };
   int i = v0;
   for (; i + D <= v1; i += D) {
@@ -675,13 +717,21 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       advance(i + d);
       float ax0, ay0, ax1, ay1;
       partial(gb[d], ms[d], ax0, ay0);
-      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
       partial(gb[d + 1], ms[d + 1], ax1, ay1);
-      gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
+      if (MODE != 2) gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
       const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
       place(i + d, s.x, s.y);
+      if (MODE == 2) {
+        scatter(gb[d], ms[d], cval(i + d, s.x, s.y));
+        gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      }
       advance(i + d + 1);  // the pair may straddle a chunk boundary
       place(i + d + 1, s.z, s.w);
+      if (MODE == 2) {
+        scatter(gb[d + 1], ms[d + 1], cval(i + d + 1, s.z, s.w));
+        gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
+      }
     }
     if constexpr (D & 1) single(D - 1, i + D - 1);
   }
@@ -693,6 +743,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       partial(gb[d], ms[d], ax, ay);
       const float2 s = lane_sum1(ax, ay);
       place(i + d, s.x, s.y);
+      if (MODE == 2) scatter(gb[d], ms[d], cval(i + d, s.x, s.y));
     }
   }
   if (cb < v1) flush();
@@ -743,7 +794,13 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
       tile[e] = grid[(size_t)gr * a.Kx + gc];
     }
     if (tid == 0) tile[P * P] = make_float2(0.f, 0.f);  // the zero cell
+    // MODE 2: one accumulator per wave (P*P cells and 64 spare cells) behind
+    // the tile, its zero cell and the norms
+    const int acells = P * P + 64, a0 = P * P + 16;
+    if (MODE == 2)
+      for (int e = tid; e < kGatherWaves * acells; e += 64 * kGatherWaves) tile[a0 + e] = make_float2(0.f, 0.f);
     __syncthreads();
+    const uint32_t ab = lds_offset(tile) + (uint32_t)(a0 + w * acells) * 8u;
     // (selects, not indexing: a run-time index would move the item to scratch)
     const int wv0 = w == 0 ? item.v0 : w == 1 ? item.wv[0] : w == 2 ? item.wv[1] : item.wv[2];
     const int wv1 = w == kGatherWaves - 1 ? item.v1 : w == 0 ? item.wv[0] : w == 1 ? item.wv[1] : item.wv[2];
@@ -757,7 +814,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
   case K:                                                                                              \
     if constexpr (K <= NKM)                                                                            \
       wtap = gather_item<GP, MODE, K, Depth<GP, K, PHI_GATHER_DEPTH_REGS>::value>(a, item, r0, r1, wtap, \
-                                                                                  vis, yv, rho2, res2, tile); \
+                                                                                  vis, yv, rho2, res2, tile, ab); \
     break;
         PHI_G_CASE(1)
         PHI_G_CASE(2)
@@ -772,7 +829,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
       }
       r0 = r1;
     }
-    if (MODE == 1) {
+    if (MODE >= 1) {
       rho2 = wave_sum_d(rho2);
       res2 = wave_sum_d(res2);
       if (lane == 0) {
@@ -788,6 +845,18 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
         }
         item_norms[2 * (int64_t)it] = r0;
         item_norms[2 * (int64_t)it + 1] = r1;
+      }
+    }
+    if (MODE == 2) {  // the item's partial: the waves' accumulators in a fixed order
+      float2* __restrict__ out = a.partials + item.poff;
+      for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
+        float2 s = tile[a0 + e];
+        for (int q = 1; q < kGatherWaves; ++q) {
+          const float2 t = tile[a0 + q * acells + e];
+          s.x += t.x;
+          s.y += t.y;
+        }
+        out[e] = s;
       }
     }
     __syncthreads();
@@ -1141,12 +1210,20 @@ __global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__
 // those of the tiles up to `halo` tiles above/left, with wrap).  The partial
 // list is staged in LDS once per tile; reads of a partial row are coalesced.
 constexpr int kMergeList = 256;
+// Factor of an item's partial in the merge: sigma_b * scale_b after the fused
+// dual step (its partials hold G^H theta c), else 1 (exact: fma(1, v, s) = s + v).
+__device__ __forceinline__ float merge_factor(const double* sigma, const double* scale, int blk) {
+  return scale ? (float)((sigma ? sigma[blk] : 1.0) * scale[blk]) : 1.f;
+}
+
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
                                                const TileEntry* __restrict__ ent, int Ky, int Kx, int T,
-                                               int halo, int l0) {
+                                               int halo, int l0, const double* __restrict__ sigma,
+                                               const double* __restrict__ scale) {
   __shared__ int64_t s_off[kMergeList];
   __shared__ int32_t s_pitch[kMergeList];
+  __shared__ float s_fac[kMergeList];
   __shared__ int32_t s_oy[kMergeList], s_ox[kMergeList];
   __shared__ int s_beg[16], s_pre[17];
   const int l = l0 + blockIdx.y;
@@ -1175,6 +1252,7 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
     const TileEntry te = ent[s_beg[j] + (e - s_pre[j])];
     s_off[e] = te.poff;
     s_pitch[e] = te.pitch;
+    s_fac[e] = merge_factor(sigma, scale, te.blk);
     s_oy[e] = (j / hw) * T;
     s_ox[e] = (j % hw) * T;
   }
@@ -1188,8 +1266,8 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
         const int ly = r + s_oy[k], lx = c + s_ox[k], P = s_pitch[k];
         if (ly < P && lx < P) {
           const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
-          sx += v.x;
-          sy += v.y;
+          sx = __builtin_fmaf(s_fac[k], v.x, sx);
+          sy = __builtin_fmaf(s_fac[k], v.y, sy);
         }
       }
     } else {  // long lists: same order, read from global memory
@@ -1205,8 +1283,9 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
             const TileEntry te = ent[k];
             if (ly < te.pitch && lx < te.pitch) {
               const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
-              sx += v.x;
-              sy += v.y;
+              const float f = merge_factor(sigma, scale, te.blk);
+              sx = __builtin_fmaf(f, v.x, sx);
+              sy = __builtin_fmaf(f, v.y, sy);
             }
           }
         }
@@ -1589,6 +1668,18 @@ __global__ __launch_bounds__(64) void k_build_g(BuildArgs a, int it0) {
   }
 }
 
+// v+ = sigma_b scale_b c over the visibilities of each item (fused dual step)
+__global__ __launch_bounds__(256) void k_vscale(const Item* __restrict__ items, float2* __restrict__ vis,
+                                                const double* __restrict__ sigma, const double* __restrict__ scale,
+                                                int it0) {
+  const Item item = items[it0 + blockIdx.x];
+  const float f = (float)((sigma ? sigma[item.blk] : 1.0) * scale[item.blk]);
+  for (int v = item.v0 + threadIdx.x; v < item.v1; v += 256) {
+    const float2 c = vis[v];
+    vis[v] = make_float2(f * c.x, f * c.y);
+  }
+}
+
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
 // Threads of a row transform: a row of 4096 or more points fills 32-64 KiB of
@@ -1772,8 +1863,15 @@ static hipError_t gather_m(int nkc, const GArgs& a, float2* vis, const float2* y
 template <int GP>
 static hipError_t gather_gp(int mode, int nkc, const GArgs& a, float2* vis, const float2* y, double* norms,
                             size_t lds, int it0, int it1, int nb, hipStream_t s) {
-  return mode == 0 ? gather_m<GP, 0>(nkc, a, vis, y, norms, lds, it0, it1, nb, s)
-                   : gather_m<GP, 1>(nkc, a, vis, y, norms, lds, it0, it1, nb, s);
+  return mode == 0   ? gather_m<GP, 0>(nkc, a, vis, y, norms, lds, it0, it1, nb, s)
+         : mode == 1 ? gather_m<GP, 1>(nkc, a, vis, y, norms, lds, it0, it1, nb, s)
+                     : gather_m<GP, 2>(nkc, a, vis, y, norms, lds, it0, it1, nb, s);
+}
+
+size_t fused_lds_bytes(int max_pitch) {
+  const size_t pp = (size_t)max_pitch * max_pitch;
+  const size_t bytes = (pp + 16 + (size_t)kGatherWaves * (pp + 64)) * sizeof(float2);
+  return bytes <= 65536 ? bytes : 0;
 }
 
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y, double* item_norms,
@@ -1781,9 +1879,11 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
   const int n = it1 - it0;
   if (n <= 0) return hipSuccess;
   const int nb = grid_blocks > 0 && grid_blocks < n ? grid_blocks : n;
-  const size_t lds = ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell, wave norms
-  if (lds > 65536) return hipErrorInvalidValue;
+  const size_t lds = mode == 2 ? fused_lds_bytes(max_pitch)
+                               : ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell, norms
+  if (lds == 0 || lds > 65536) return hipErrorInvalidValue;
   if (gprec == 3) {
+    if (mode == 2) return hipErrorInvalidValue;  // the Kaiser-Bessel mode has its own scatter
     const dim3 g(nb), b(64 * kGatherWaves);
 #define PHI_KB_G(JJ)                                                                                       \
   case JJ:                                                                                                 \
@@ -1868,10 +1968,11 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 }
 
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
-                        int Ky, int Kx, int T, int halo, int l0, int nl, hipStream_t s) {
+                        int Ky, int Kx, int T, int halo, int l0, int nl, const double* sigma, const double* scale,
+                        hipStream_t s) {
   const int tiles = (Ky / T) * (Kx / T);
   hipLaunchKernelGGL(k_merge, dim3(tiles, nl), dim3(256), 0, s, grid, partials, tile_ptr, entries, Ky, Kx, T, halo,
-                     l0);
+                     l0, sigma, scale);
   return hipGetLastError();
 }
 
@@ -1938,6 +2039,13 @@ hipError_t launch_eps_update(const double* res, const double* var, const BlockIn
 hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s) {
   if (it1 <= it0) return hipSuccess;
   hipLaunchKernelGGL(k_build_g, dim3(it1 - it0), dim3(64), 0, s, a, it0);
+  return hipGetLastError();
+}
+
+hipError_t launch_vscale(const Item* items, float2* vis, const double* sigma, const double* scale, int it0, int it1,
+                         hipStream_t s) {
+  if (it1 <= it0) return hipSuccess;
+  hipLaunchKernelGGL(k_vscale, dim3(it1 - it0), dim3(256), 0, s, items, vis, sigma, scale, it0);
   return hipGetLastError();
 }
 

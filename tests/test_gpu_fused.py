@@ -1,0 +1,68 @@
+"""The fused dual step (each G tap read once: c and G^H theta c in one pass,
+the per-block factor sigma_b * scale_b applied to v+ and in the merge,
+G^H(s c) = s G^H c; PHI_FUSED_GH) against the separate passes and the
+FP64 oracle, through the C ABI.  The fused pass keeps the item's grid tile
+and one accumulator per wave in LDS, so it runs where that fits a work-group
+(16-cell tiles here); elsewhere the plan keeps the separate passes."""
+import sys
+
+import numpy as np
+import pytest
+
+from _cases import Case, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+_CACHE = {}
+
+
+def case(name):
+    if name not in _CACHE:
+        _CACHE[name] = Case(name)
+    return _CACHE[name]
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.mark.parametrize("name,prec", [("tiny_w", "c64"), ("tiny_dde", "c64"), ("C2s", "c64"), ("C2s", "f16"),
+                                       ("C3s", "bf16"), ("C4s", "c64")])
+def test_fused_matches_separate_and_oracle(name, prec):
+    from test_gpu_parity import gpu_dual
+    from paper_2209_07604_amd import FUSED_GH, GRAPH
+    import oracle
+    _say("[fused]", name, prec)
+    c = case(name)
+    plan = c.plan(g_prec=prec)
+    plan.set_tuning(16, 0)          # 16-cell tiles: the fused pass's LDS fits (the bench's autotuned tile)
+    info_s = plan.info()
+    plan.set_flags(FUSED_GH)
+    info_f = plan.info()
+    # the fused pass is in use: one G read per dual step instead of two
+    assert info_f["alg_bytes_dual_step"] < info_s["alg_bytes_dual_step"]
+    nb = len(c.blocks)
+    sigma = np.linspace(0.8, 1.2, nb)
+    fus = gpu_dual(c, plan, c.V, c.eps, sigma)
+    plan.set_flags(FUSED_GH | GRAPH)
+    fus_g = gpu_dual(c, plan, c.V, c.eps, sigma)
+    plan.set_flags(0)
+    sep = gpu_dual(c, plan, c.V, c.eps, sigma)
+    for a_, b_ in zip(fus, fus_g):                    # graph replay equals the eager step
+        assert all(np.array_equal(x, y) for x, y in zip(a_, b_)) if isinstance(a_, list) else np.array_equal(a_, b_)
+    op = c.op if prec == "c64" else c.operator(c.theta, prec=prec)
+    Vp_o, grad_o, rho_o, res_o = oracle.dual_step(op, {l: x.astype(np.float64) for l, x in c.Xt.items()},
+                                                  c.V, c.Y, c.eps, sigma)
+    Vp_f, grad_f, rho_f, res_f = fus
+    Vp_s, grad_s, rho_s, res_s = sep
+    ev = rel_l2(np.concatenate(Vp_f), np.concatenate(Vp_o))
+    _say("  v+ vs oracle", ev, "vs separate", rel_l2(np.concatenate(Vp_f), np.concatenate(Vp_s)))
+    assert ev <= 1e-5
+    assert rel_l2(rho_f, rho_o) <= 1e-5 and rel_l2(res_f, res_o) <= 1e-5
+    assert np.array_equal(rho_f, rho_s) and np.array_equal(res_f, res_s)   # same gather, same norms
+    for l in range(c.prob.L):
+        e = rel_l2(grad_f[l], grad_o[l])
+        _say("  grad ch", l, "vs oracle", e, "vs separate", rel_l2(grad_f[l], grad_s[l]))
+        assert e <= 1e-5
