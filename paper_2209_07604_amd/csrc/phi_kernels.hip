@@ -247,45 +247,74 @@ __device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ 
   }
 }
 
-// Z then the forward DFT of one image row (grid length N = Kx = 2 Nx).
+// Z then the forward DFT of one image row (grid length N = Kx = 2 Nx).  The
+// row is real, so it runs as one complex transform of half the length on
+// z[m] = r[2m] + i r[2m+1]: with Z = DFT_{N/2}(z), E[k] = (Z[k] + conj(Z[-k]))/2
+// and O[k] = (Z[k] - conj(Z[-k]))/(2i) are the transforms of the even and odd
+// samples, and R[k] = E[k] + w^k O[k], R[k + N/2] = E[k] - w^k O[k]
+// (w = exp(-2 pi i / N)).
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, float2* __restrict__ half,
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
-  __shared__ float2 buf[N];
+  constexpr int M = N / 2;
+  __shared__ float2 buf[M];
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
-  for (int k = threadIdx.x; k < N; k += NT) {
-    const int qb = k < N / 2 ? k : k - N;
-    const int q = qb + Nx / 2;
-    float v = 0.f;
-    if (q >= 0 && q < Nx) v = syp * sx[q] * xr[q];
-    buf[k] = make_float2(v, 0.f);
-  }
+  auto sample = [&](int n) {  // Z x at grid column n
+    const int q = (n < N / 2 ? n : n - N) + Nx / 2;
+    return (q >= 0 && q < Nx) ? syp * sx[q] * xr[q] : 0.f;
+  };
+  for (int m = threadIdx.x; m < M; m += NT) buf[m] = make_float2(sample(2 * m), sample(2 * m + 1));
   __syncthreads();
-  fft_run<N, 1, NT, false, 1>(buf, tw);
+  fft_run<M, 1, NT, false, 1, 2>(buf, tw);
   float2* out = half + ((size_t)l * Ny + p) * N;
-  for (int k = threadIdx.x; k < N; k += NT) out[k] = buf[k];
+  for (int kk = threadIdx.x; kk < M; kk += NT) {
+    const float2 a = buf[kk], b = buf[kk == 0 ? 0 : M - kk];
+    const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));  // (Z[k] + conj(Z[-k])) / 2
+    const float2 o = make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));  // (Z[k] - conj(Z[-k])) / (2i)
+    const float2 wo = cmul(tw[kk], o);
+    out[kk] = make_float2(e.x + wo.x, e.y + wo.y);
+    out[kk + M] = make_float2(e.x - wo.x, e.y - wo.y);
+  }
 }
 
-// Inverse DFT of one half-grid row, then Z^T: crop, scale, real part.
+// Inverse DFT of one half-grid row, then Z^T: crop, scale, real part.  Only
+// Re(IDFT(H)) is kept, which is the IDFT of the Hermitian part
+// Hs[k] = (H[k] + conj(H[-k]))/2, a real sequence a[n]; its even and odd
+// samples come from one complex inverse transform of half the length:
+// z = IDFT_{N/2}(Fe + i Fo), Fe[k] = Hs[k] + Hs[k + N/2],
+// Fo[k] = (Hs[k] - Hs[k + N/2]) w^-k, a[2m] = Re z[m], a[2m+1] = Im z[m].
 template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ half, float* __restrict__ x,
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
-  __shared__ float2 buf[N];
+  constexpr int M = N / 2;
+  __shared__ float2 buf[M];
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float2* in = half + ((size_t)l * Ny + p) * N;
-  for (int k = threadIdx.x; k < N; k += NT) buf[k] = in[k];
+  auto herm = [&](int k) {  // Hs[k]
+    const float2 a = in[k], b = in[k == 0 ? 0 : N - k];
+    return make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));
+  };
+  for (int kk = threadIdx.x; kk < M; kk += NT) {
+    const float2 h0 = herm(kk), h1 = herm(kk + M);
+    const float2 fe = make_float2(h0.x + h1.x, h0.y + h1.y);
+    float2 w = tw[kk];
+    w.y = -w.y;  // w^-k
+    const float2 fo = cmul(make_float2(h0.x - h1.x, h0.y - h1.y), w);
+    buf[kk] = make_float2(fe.x - fo.y, fe.y + fo.x);  // Fe + i Fo
+  }
   __syncthreads();
-  fft_run<N, 1, NT, true, 1>(buf, tw);
+  fft_run<M, 1, NT, true, 1, 2>(buf, tw);
   float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
   for (int q = threadIdx.x; q < Nx; q += NT) {
-    int k = q - Nx / 2;
-    if (k < 0) k += N;
-    xr[q] = buf[k].x * syp * sx[q];
+    int n = q - Nx / 2;
+    if (n < 0) n += N;
+    const float2 z = buf[n >> 1];
+    xr[q] = ((n & 1) ? z.y : z.x) * syp * sx[q];
   }
 }
 
@@ -1682,11 +1711,11 @@ __global__ __launch_bounds__(256) void k_vscale(const Item* __restrict__ items, 
 
 // ------------------------------------------------------------- launchers
 constexpr int kFftThreads = 256;
-// Threads of a row transform: a row of 4096 or more points fills 32-64 KiB of
-// LDS, so few work-groups fit on a compute unit; give each more waves.
+// Threads of a row transform: one per radix-8 butterfly of the half-length
+// complex transform (N/16), 64 to 512.
 template <int N>
 constexpr int row_threads() {
-  return N >= 4096 ? 512 : kFftThreads;
+  return N / 16 < 64 ? 64 : N / 16 > 512 ? 512 : N / 16;
 }
 // Column panels of 32 KiB or more likewise get 512 threads, 64 KiB ones 1024.
 template <int CELLS>
