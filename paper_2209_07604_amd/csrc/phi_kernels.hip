@@ -514,9 +514,9 @@ __device__ __forceinline__ float4 lane_sum2(float p0, float p1, float q0, float 
 // (uniform).  Lanes past a smaller window read the next window's taps (or the
 // zero pad behind G); their products meet the zero cell (gather) or the
 // lane's spare cell (scatter), so they never reach a result.  The window's
-// metadata word comes from two 64-visibility chunks held one per lane (the
-// fetch runs up to D windows ahead).
-template <int GP, int NK>
+// metadata word comes from two C-visibility chunks held one per lane (the
+// fetch runs up to D <= C windows ahead).
+template <int GP, int NK, int C>
 struct GStream {
   using R = typename GRaw<GP>::T;
   const char* __restrict__ G;
@@ -525,10 +525,10 @@ struct GStream {
   int j, v1;
   __device__ __forceinline__ void fetch(R (&g)[NK], uint32_t& m, uint32_t mcur, uint32_t mnxt, int cb, int lane) {
     const bool live = j < v1;
-    const int rel = j - cb;  // < 64 + D
+    const int rel = j - cb;  // < C + D
     const uint32_t ma = (uint32_t)__builtin_amdgcn_readlane((int)mcur, rel & 63);
-    const uint32_t mb = (uint32_t)__builtin_amdgcn_readlane((int)mnxt, rel & 63);
-    const uint32_t mt = live ? (rel < 64 ? ma : mb) : 0u;
+    const uint32_t mb = (uint32_t)__builtin_amdgcn_readlane((int)mnxt, (rel - C) & 63);
+    const uint32_t mt = live ? (rel < C ? ma : mb) : 0u;
     m = mt;
     const int s = 2 * (int)(mt >> 26) + 1;
     const R* __restrict__ gp = reinterpret_cast<const R*>(G) + (live ? tap : tap_end);
@@ -538,6 +538,15 @@ struct GStream {
     ++j;
   }
 };
+
+// Windows per chunk for a prefetch depth of D windows: the largest multiple
+// of D that fits a wave, so every chunk starts at ring slot 0 and the chunk
+// bookkeeping (metadata rotation, per-visibility vectors, stores) sits at one
+// point between groups of D windows instead of inside them.
+template <int D>
+constexpr int chunk_len() {
+  return D * (64 / D);
+}
 
 // Per-S lane layout of a window inside a pitch-P LDS tile: the byte offset of
 // each step's cell from the window origin.  Lanes past the window hold a
@@ -608,35 +617,35 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
                                             double& rho2, double& res2, const float2* __restrict__ tile,
                                             uint32_t ab = 0) {
   using R = typename GRaw<GP>::T;
+  constexpr int C = chunk_len<D>();
   const int lane = threadIdx.x & 63;
   const int vlast = v1 - 1, P = item.pitch;
   const float th = a.theta[item.blk];
   float inv_sig = 1.f;
   if (MODE >= 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
-  // 64-visibility chunks held one value per lane: metadata of chunks cb and
-  // cb + 64 (read per window) with cb + 128 in flight; v and y of chunk cb
-  // (read at its flush) with cb + 64 in flight.  Per-window code only reads
-  // registers that were filled by moves at a chunk boundary, so no wait for a
-  // chunk load falls between a window's G fetch and its use (such a wait
-  // would drain the whole prefetch).
+  // C-visibility chunks held one value per lane (lanes < C): metadata of
+  // chunks cb and cb + C (read per window) with cb + 2C in flight; v and y of
+  // chunk cb (read at its flush) with cb + C in flight.  These registers are
+  // only rotated between chunks, so no wait for a chunk load falls between a
+  // window's G fetch and its use (such a wait would drain the prefetch).
   int cb = v0;
   uint32_t mcur = a.meta[min(cb + lane, vlast)];
-  uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
-  uint32_t mstg = a.meta[min(cb + 128 + lane, vlast)];
+  uint32_t mnxt = a.meta[min(cb + C + lane, vlast)];
+  uint32_t mstg = a.meta[min(cb + 2 * C + lane, vlast)];
   float2 vc = make_float2(0.f, 0.f), yc = vc, vstg = vc, ystg = vc;
   if (MODE >= 1) {
     vc = vis[min(cb + lane, vlast)];
     yc = yv[min(cb + lane, vlast)];
-    vstg = vis[min(cb + 64 + lane, vlast)];
-    ystg = yv[min(cb + 64 + lane, vlast)];
+    vstg = vis[min(cb + C + lane, vlast)];
+    ystg = yv[min(cb + C + lane, vlast)];
   }
   R gb[D][NK];
   uint32_t ms[D];
-  GStream<GP, NK> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
+  GStream<GP, NK, C> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
   TapLayout<NK> lay;
   float2 res = make_float2(0.f, 0.f);  // lane i: sum for visibility cb + i (theta applied at flush)
   auto flush = [&]() {
-    if (cb + lane < v1) {
+    if (lane < C && cb + lane < v1) {
       const float px = th * res.x, py = th * res.y;
       if (MODE == 0) {
         vis[cb + lane] = make_float2(px, py);
@@ -649,21 +658,18 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       }
     }
   };
-  auto advance = [&](int i) {
-    if (i == cb + 64) {
-      flush();
-      cb += 64;
-      mcur = mnxt;
-      mnxt = mstg;
-      mstg = a.meta[min(cb + 128 + lane, vlast)];
-      if (MODE >= 1) {
-        vc = vstg;
-        yc = ystg;
-        vstg = vis[min(cb + 64 + lane, vlast)];
-        ystg = yv[min(cb + 64 + lane, vlast)];
-      }
-      res = make_float2(0.f, 0.f);
+  auto rotate = [&]() {
+    cb += C;
+    mcur = mnxt;
+    mnxt = mstg;
+    mstg = a.meta[min(cb + 2 * C + lane, vlast)];
+    if (MODE >= 1) {
+      vc = vstg;
+      yc = ystg;
+      vstg = vis[min(cb + C + lane, vlast)];
+      ystg = yv[min(cb + C + lane, vlast)];
     }
+    res = make_float2(0.f, 0.f);
   };
   // this lane's partial (sum over its taps of g * X) for one window; lanes
   // past the window read the zero cell behind the tile
@@ -688,18 +694,18 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       }
     }
   };
-  auto place = [&](int i, float px, float py) {
-    const bool me = lane == i - cb;  // i - cb is wave-uniform
+  auto place = [&](int rel, float px, float py) {  // rel = visibility - cb, wave-uniform
+    const bool me = lane == rel;
     res.x = me ? px : res.x;
     res.y = me ? py : res.y;
   };
-  // MODE 2: c of window i from its sum (the same operations as the flush, so
+  // MODE 2: c of a window from its sum (the same operations as the flush, so
   // the c added here is the c written to v), then conj(g) theta c into the
   // accumulator: read the window's cells, add, write (distinct cells)
-  auto cval = [&](int i, float sx, float sy) {
+  auto cval = [&](int rel, float sx, float sy) {
     const float px = th * sx, py = th * sy;
-    const float vx = readlane_f(vc.x, i - cb), vy = readlane_f(vc.y, i - cb);
-    const float yx = readlane_f(yc.x, i - cb), yy = readlane_f(yc.y, i - cb);
+    const float vx = readlane_f(vc.x, rel), vy = readlane_f(vc.y, rel);
+    const float yx = readlane_f(yc.x, rel), yy = readlane_f(yc.y, rel);
     return make_float2(__builtin_fmaf(vx, inv_sig, px) - yx, __builtin_fmaf(vy, inv_sig, py) - yy);
   };
   const uint32_t apark = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
@@ -727,55 +733,65 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   };
 #pragma unroll
   for (int d = 0; d < D; ++d) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
-  auto single = [&](int d, int i) {
-    advance(i);
+  // window at slot d of a group (rel = its offset in the chunk); fetch > 0
+  // refills the slot with the window D ahead
+  auto single = [&](int d, int rel, bool refill) {
     float ax, ay;
     partial(gb[d], ms[d], ax, ay);
-    if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+    if (MODE != 2 && refill) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
     const float2 s = lane_sum1(ax, ay);
-    place(i, s.x, s.y);
+    place(rel, s.x, s.y);
     if (MODE == 2) {
-      scatter(gb[d], ms[d], cval(i, s.x, s.y));
-      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      scatter(gb[d], ms[d], cval(rel, s.x, s.y));
+      if (refill) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
     }
   };
-  int i = v0;
-  for (; i + D <= v1; i += D) {
+  // A slot's refill must not be issued before the slot's old taps are
+  // consumed: if both are live at once, the slot needs a second register
+  // and the copy back at the end of the group waits for the refill load,
+  // which drains the whole prefetch.  The partial sums are pinned here (an
+  // empty statement that takes them and orders memory accesses around it).
+  auto settle = [](float& x, float& y) { asm volatile("" : "+v"(x), "+v"(y) : : "memory"); };
+  // one group: D windows at slots 0..D-1, reduced in pairs
+  auto group = [&](int rel0) {
 #pragma unroll
     for (int d = 0; d + 1 < D; d += 2) {
-      advance(i + d);
       float ax0, ay0, ax1, ay1;
       partial(gb[d], ms[d], ax0, ay0);
+      settle(ax0, ay0);
       if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
       partial(gb[d + 1], ms[d + 1], ax1, ay1);
+      settle(ax1, ay1);
       if (MODE != 2) gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
       const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
-      place(i + d, s.x, s.y);
+      place(rel0 + d, s.x, s.y);
       if (MODE == 2) {
-        scatter(gb[d], ms[d], cval(i + d, s.x, s.y));
+        scatter(gb[d], ms[d], cval(rel0 + d, s.x, s.y));
         gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
       }
-      advance(i + d + 1);  // the pair may straddle a chunk boundary
-      place(i + d + 1, s.z, s.w);
+      place(rel0 + d + 1, s.z, s.w);
       if (MODE == 2) {
-        scatter(gb[d + 1], ms[d + 1], cval(i + d + 1, s.z, s.w));
+        scatter(gb[d + 1], ms[d + 1], cval(rel0 + d + 1, s.z, s.w));
         gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
       }
     }
-    if constexpr (D & 1) single(D - 1, i + D - 1);
-  }
+    if constexpr (D & 1) single(D - 1, rel0 + D - 1, true);
+  };
+  for (;;) {
+    const int n = min(C, v1 - cb);  // windows of this chunk
+    const int full = n - n % D;     // in whole groups
+    for (int rel = 0; rel < full; rel += D) group(rel);
+    if (n < C) {  // last chunk: the rest (< D windows) is already fetched
 #pragma unroll
-  for (int d = 0; d < D - 1; ++d) {
-    if (i + d < v1) {
-      advance(i + d);
-      float ax, ay;
-      partial(gb[d], ms[d], ax, ay);
-      const float2 s = lane_sum1(ax, ay);
-      place(i + d, s.x, s.y);
-      if (MODE == 2) scatter(gb[d], ms[d], cval(i + d, s.x, s.y));
+      for (int d = 0; d < D - 1; ++d)
+        if (full + d < n) single(d, full + d, false);
+      flush();
+      break;
     }
+    flush();
+    if (cb + C >= v1) break;
+    rotate();
   }
-  if (cb < v1) flush();
   return gs.tap;
 }
 
@@ -904,6 +920,7 @@ template <int GP, int MODE, int NK, int D>
 __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
                                                 float2* __restrict__ vis, float2* __restrict__ acc) {
   using R = typename GRaw<GP>::T;
+  constexpr int C = chunk_len<D>();
   const int lane = threadIdx.x;
   const int vlast = v1 - 1, P = item.pitch;
   const uint32_t ab = lds_offset(acc);
@@ -911,39 +928,33 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
   const float th = a.theta[item.blk];
   float sc = 1.f;
   if (MODE == 1) sc = (float)((a.sigma ? a.sigma[item.blk] : 1.0) * a.scale[item.blk]);
-  // theta * v for a chunk (dual form: v+ = sigma * scale * c, written back)
+  // theta * v for a chunk (dual form: v+ = sigma * scale * c, written back;
+  // lanes past the chunk hold the next chunk's visibilities and leave them)
   auto take_av = [&](float2 v, int c0) -> float2 {
     if (MODE == 1) {
       v = make_float2(sc * v.x, sc * v.y);
-      if (c0 + lane < v1) vis[c0 + lane] = v;
+      if (lane < C && c0 + lane < v1) vis[c0 + lane] = v;
     }
     return make_float2(th * v.x, th * v.y);
   };
-  // chunks as in the gather: metadata of chunks cb, cb + 64 and (in flight)
-  // cb + 128; theta v of chunk cb (read per window) and raw v of cb + 64
+  // chunks as in the gather: metadata of chunks cb, cb + C and (in flight)
+  // cb + 2C; theta v of chunk cb (read per window) and raw v of cb + C, all
+  // rotated between chunks only
   int cb = v0;
   uint32_t mcur = a.meta[min(cb + lane, vlast)];
-  uint32_t mnxt = a.meta[min(cb + 64 + lane, vlast)];
-  uint32_t mstg = a.meta[min(cb + 128 + lane, vlast)];
+  uint32_t mnxt = a.meta[min(cb + C + lane, vlast)];
+  uint32_t mstg = a.meta[min(cb + 2 * C + lane, vlast)];
   float2 avc = take_av(vis[min(cb + lane, vlast)], cb);
-  float2 vraw = vis[min(cb + 64 + lane, vlast)];
+  float2 vraw = vis[min(cb + C + lane, vlast)];
   R gb[D][NK];
   uint32_t ms[D];
-  GStream<GP, NK> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
+  GStream<GP, NK, C> gs{static_cast<const char*>(a.G), uniform64(tap0), uniform64(tap0), v0, v1};
   TapLayout<NK> lay;
-  auto step = [&](const R(&g)[NK], uint32_t mt, int i) {
-    if (i == cb + 64) {
-      cb += 64;
-      mcur = mnxt;
-      mnxt = mstg;
-      mstg = a.meta[min(cb + 128 + lane, vlast)];
-      avc = take_av(vraw, cb);
-      vraw = vis[min(cb + 64 + lane, vlast)];
-    }
+  auto step = [&](const R(&g)[NK], uint32_t mt, int rel) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
-    const float vx = readlane_f(avc.x, i - cb), vy = readlane_f(avc.y, i - cb);
+    const float vx = readlane_f(avc.x, rel), vy = readlane_f(avc.y, rel);
     const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
     // all steps of one window touch distinct cells: read them all, then add
     // and write, so the window costs one LDS round trip, not one per step
@@ -965,17 +976,30 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
   };
 #pragma unroll
   for (int d = 0; d < D; ++d) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
-  int i = v0;
-  for (; i + D <= v1; i += D) {
+  for (;;) {
+    const int n = min(C, v1 - cb);  // windows of this chunk
+    const int full = n - n % D;     // in whole groups of D (slots 0..D-1)
+    for (int rel = 0; rel < full; rel += D) {
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      step(gb[d], ms[d], i + d);
-      gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      for (int d = 0; d < D; ++d) {
+        step(gb[d], ms[d], rel + d);
+        gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+      }
     }
-  }
+    if (n < C) {  // last chunk: the rest (< D windows) is already fetched
 #pragma unroll
-  for (int d = 0; d < D - 1; ++d)
-    if (i + d < v1) step(gb[d], ms[d], i + d);
+      for (int d = 0; d < D - 1; ++d)
+        if (full + d < n) step(gb[d], ms[d], full + d);
+      break;
+    }
+    if (cb + C >= v1) break;
+    cb += C;
+    mcur = mnxt;
+    mnxt = mstg;
+    mstg = a.meta[min(cb + 2 * C + lane, vlast)];
+    avc = take_av(vraw, cb);
+    vraw = vis[min(cb + C + lane, vlast)];
+  }
   return gs.tap;
 }
 
