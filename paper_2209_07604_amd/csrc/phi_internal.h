@@ -37,7 +37,7 @@ struct Item {
 };
 static_assert(sizeof(Item) == 80, "Item layout");
 #ifndef PHI_GATHER_WAVES
-#define PHI_GATHER_WAVES 4
+#define PHI_GATHER_WAVES 2
 #endif
 constexpr int kGatherWaves = PHI_GATHER_WAVES;
 
