@@ -12,7 +12,9 @@ launched per channel), batched FP32, batched FP16-G (the headline), batched
 BF16-G; batched forms replay a hipGraph.  On direction-independent workloads
 (one window size) the form batched_kb evaluates the Kaiser-Bessel taps in the
 kernels instead of reading stored G; fused_<prec> runs the dual step in one
-pass over G (PHI_FUSED_GH).
+pass over G (PHI_FUSED_GH).  The autotuner picks one pass or two for the
+batched forms; twopass_<prec> times the same tuning with gather and scatter as
+separate passes, reported as roofline_two_pass.
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
 """
@@ -313,7 +315,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C2")
-    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_f16,batched_bf16")
+    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_f16,twopass_f16,batched_bf16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile edge (skips the autotuner)")
@@ -418,14 +420,16 @@ def main():
         grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
         rho = torch.empty(nblk, dtype=torch.float64, device=dev)
         res = torch.empty(nblk, dtype=torch.float64, device=dev)
-        if kind in ("batched", "fused") and args.tile:
+        if kind in ("batched", "fused", "twopass") and args.tile:
             p.set_tuning(args.tile, args.persist)
         elif kind in ("batched", "fused") and not args.no_autotune:
             rc = p.autotune(3)
             log("[bench] autotune %s -> rc %d, tile %d, persist %d" % (
                 prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
         # the autotuner may have chosen the one-pass dual step (info "fused");
-        # fused_<prec> forces it, plain_<prec> never uses it
+        # fused_<prec> forces it; plain_<prec> and twopass_<prec> (the batched
+        # form on the same tuning, gather and scatter as separate passes) never
+        # use it
         fused = kind == "fused" or (kind == "batched" and bool(p.info()["fused"]))
         flags_now = (p.info()["persist_blocks"] and PERSISTENT) | (FUSED_GH if fused else 0)
         p.set_flags((PER_CHANNEL if kind == "plain" else GRAPH) | flags_now)
@@ -535,6 +539,20 @@ def main():
         "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
         "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
     }
+    two = "twopass_" + head.split("_")[1]
+    if two in results and two != head:
+        # the same step with gather and scatter as separate passes (G read
+        # twice): its dominant kernel against the same peak
+        r2 = results[two]
+        c2 = {k_: r2["stage_ms"].get(k_, 0.0) for k_ in ("gather", "scatter")}
+        d2 = max(c2, key=c2.get)
+        a2 = info["alg_bytes_scatter"] if d2 == "scatter" else info["alg_bytes_gather"]
+        ach2 = a2 / (c2[d2] * 1e-3) / 1e9
+        line["roofline_two_pass"] = {"bound": "hbm", "kernel": d2, "achieved": ach2, "peak": HBM_PEAK_GBS,
+                                     "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS, "traffic": traffic_for(d2, a2),
+                                     "alg_bytes_per_launch": a2, "avg_launch_ms": c2[d2],
+                                     "ms_per_step": r2["ms_per_step"],
+                                     "frac_of_stream_copy": ach2 / copy_gbs if copy_gbs else None}
     if "plain_c64" in results:
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
     if args.dr:
