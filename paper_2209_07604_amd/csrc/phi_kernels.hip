@@ -52,6 +52,14 @@ __device__ __forceinline__ float readlane_f(float v, int i) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), i));
 }
 
+// v_writelane_b32 (the compiler has no builtin for it; this names the LLVM
+// intrinsic): lane i of the result is the wave-uniform v, the other lanes
+// keep old.
+extern "C" __device__ int phi_writelane_i32(int v, int i, int old) __asm("llvm.amdgcn.writelane.i32");
+__device__ __forceinline__ float writelane_f(float old, float v, int i) {
+  return __int_as_float(phi_writelane_i32(__float_as_int(v), i, __float_as_int(old)));
+}
+
 // A wave-uniform 64-bit value, so that it stays in scalar registers.
 __device__ __forceinline__ int64_t uniform64(int64_t v) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
@@ -624,18 +632,22 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   float inv_sig = 1.f;
   if (MODE >= 1 && a.sigma) inv_sig = (float)(1.0 / a.sigma[item.blk]);
   // C-visibility chunks held one value per lane (lanes < C): metadata of
-  // chunks cb and cb + C (read per window) with cb + 2C in flight; v and y of
-  // chunk cb (read at its flush) with cb + C in flight.  These registers are
-  // only rotated between chunks, so no wait for a chunk load falls between a
-  // window's G fetch and its use (such a wait would drain the prefetch).
+  // chunks cb and cb + C (read per window) with cb + 2C in flight; for
+  // chunk cb, y and pre = v / sigma - y (c = theta sum + pre), with v and y
+  // of chunk cb + C in flight.  These registers are only rotated between
+  // chunks, so no wait for a chunk load falls between a window's G fetch and
+  // its use (such a wait would drain the prefetch).
   int cb = v0;
   uint32_t mcur = a.meta[min(cb + lane, vlast)];
   uint32_t mnxt = a.meta[min(cb + C + lane, vlast)];
   uint32_t mstg = a.meta[min(cb + 2 * C + lane, vlast)];
-  float2 vc = make_float2(0.f, 0.f), yc = vc, vstg = vc, ystg = vc;
+  float2 pre = make_float2(0.f, 0.f), yc = pre, vstg = pre, ystg = pre;
+  auto pre_of = [&](float2 v, float2 y) {
+    return make_float2(__builtin_fmaf(v.x, inv_sig, -y.x), __builtin_fmaf(v.y, inv_sig, -y.y));
+  };
   if (MODE >= 1) {
-    vc = vis[min(cb + lane, vlast)];
     yc = yv[min(cb + lane, vlast)];
+    pre = pre_of(vis[min(cb + lane, vlast)], yc);
     vstg = vis[min(cb + C + lane, vlast)];
     ystg = yv[min(cb + C + lane, vlast)];
   }
@@ -650,7 +662,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       if (MODE == 0) {
         vis[cb + lane] = make_float2(px, py);
       } else {
-        const float2 c = make_float2(__builtin_fmaf(vc.x, inv_sig, px) - yc.x, __builtin_fmaf(vc.y, inv_sig, py) - yc.y);
+        const float2 c = make_float2(__builtin_fmaf(th, res.x, pre.x), __builtin_fmaf(th, res.y, pre.y));
         vis[cb + lane] = c;
         const double rx = (double)px - (double)yc.x, ry = (double)py - (double)yc.y;
         rho2 += (double)c.x * (double)c.x + (double)c.y * (double)c.y;
@@ -664,71 +676,70 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     mnxt = mstg;
     mstg = a.meta[min(cb + 2 * C + lane, vlast)];
     if (MODE >= 1) {
-      vc = vstg;
+      pre = pre_of(vstg, ystg);
       yc = ystg;
       vstg = vis[min(cb + C + lane, vlast)];
       ystg = yv[min(cb + C + lane, vlast)];
     }
     res = make_float2(0.f, 0.f);
   };
-  // this lane's partial (sum over its taps of g * X) for one window; lanes
-  // past the window read the zero cell behind the tile
+  // lanes past a window read the zero cell behind the tile
   const uint32_t tb = lds_offset(tile);
   const uint32_t park = tb + (uint32_t)(P * P) * 8u;
-  auto partial = [&](const R(&g)[NK], uint32_t mt, float& ax, float& ay) {
+  // Every window of a run has NK steps (S^2 > 64 (NK - 1)), so each step
+  // holds taps and the NK cell reads go out together, without branches.
+  auto cells = [&](uint32_t mt, float2(&X)[NK]) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
-    const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
     const uint32_t base_b = tb + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) X[k] = lds_load(lay.addr(base_b, k, park));
+  };
+  auto dot = [&](const R(&g)[NK], const float2(&X)[NK], float& ax, float& ay) {
     ax = 0.f;
     ay = 0.f;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      if (k * 64 < S2) {
-        const float2 X = lds_load(lay.addr(base_b, k, park));
-        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
-        ax = __builtin_fmaf(gx, X.x, ax);
-        ax = __builtin_fmaf(-gy, X.y, ax);
-        ay = __builtin_fmaf(gx, X.y, ay);
-        ay = __builtin_fmaf(gy, X.x, ay);
-      }
+      const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+      ax = __builtin_fmaf(gx, X[k].x, ax);
+      ax = __builtin_fmaf(-gy, X[k].y, ax);
+      ay = __builtin_fmaf(gx, X[k].y, ay);
+      ay = __builtin_fmaf(gy, X[k].x, ay);
     }
   };
-  auto place = [&](int rel, float px, float py) {  // rel = visibility - cb, wave-uniform
-    const bool me = lane == rel;
-    res.x = me ? px : res.x;
-    res.y = me ? py : res.y;
+  // this lane's partial (sum over its taps of g * X) for one window
+  auto partial = [&](const R(&g)[NK], uint32_t mt, float& ax, float& ay) {
+    float2 X[NK];
+    cells(mt, X);
+    dot(g, X, ax, ay);
+  };
+  auto place = [&](int rel, float px, float py) {  // rel = visibility - cb; rel, px, py wave-uniform
+    res.x = writelane_f(res.x, px, rel);
+    res.y = writelane_f(res.y, py, rel);
   };
   // MODE 2: c of a window from its sum (the same operations as the flush, so
   // the c added here is the c written to v), then conj(g) theta c into the
   // accumulator: read the window's cells, add, write (distinct cells)
   auto cval = [&](int rel, float sx, float sy) {
-    const float px = th * sx, py = th * sy;
-    const float vx = readlane_f(vc.x, rel), vy = readlane_f(vc.y, rel);
-    const float yx = readlane_f(yc.x, rel), yy = readlane_f(yc.y, rel);
-    return make_float2(__builtin_fmaf(vx, inv_sig, px) - yx, __builtin_fmaf(vy, inv_sig, py) - yy);
+    return make_float2(__builtin_fmaf(th, sx, readlane_f(pre.x, rel)), __builtin_fmaf(th, sy, readlane_f(pre.y, rel)));
   };
   const uint32_t apark = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
   auto scatter = [&](const R(&g)[NK], uint32_t mt, float2 c) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
-    const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
     const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
     const float vx = th * c.x, vy = th * c.y;
     float2 cur[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k)
-      if (k * 64 < S2) cur[k] = lds_load(lay.addr(base_b, k, apark));
+    for (int k = 0; k < NK; ++k) cur[k] = lds_load(lay.addr(base_b, k, apark));
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      if (k * 64 < S2) {
-        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
-        cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
-        cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
-        cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
-        cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
-        lds_store(lay.addr(base_b, k, apark), cur[k]);
-      }
+      const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+      cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
+      cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
+      cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
+      cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
+      lds_store(lay.addr(base_b, k, apark), cur[k]);
     }
   };
 #pragma unroll
@@ -757,10 +768,20 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
 #pragma unroll
     for (int d = 0; d + 1 < D; d += 2) {
       float ax0, ay0, ax1, ay1;
-      partial(gb[d], ms[d], ax0, ay0);
-      settle(ax0, ay0);
-      if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
-      partial(gb[d + 1], ms[d + 1], ax1, ay1);
+      if constexpr (NK <= 3) {  // both windows' cell reads in flight together
+        float2 X0[NK], X1[NK];
+        cells(ms[d], X0);
+        cells(ms[d + 1], X1);
+        dot(gb[d], X0, ax0, ay0);
+        settle(ax0, ay0);
+        if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+        dot(gb[d + 1], X1, ax1, ay1);
+      } else {
+        partial(gb[d], ms[d], ax0, ay0);
+        settle(ax0, ay0);
+        if (MODE != 2) gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+        partial(gb[d + 1], ms[d + 1], ax1, ay1);
+      }
       settle(ax1, ay1);
       if (MODE != 2) gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
       const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
@@ -952,26 +973,23 @@ __device__ __forceinline__ int64_t scatter_item(const GArgs& a, const Item& item
   TapLayout<NK> lay;
   auto step = [&](const R(&g)[NK], uint32_t mt, int rel) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
-    const int S2 = S * S;
     if (S != lay.S) lay.set(S, P, lane);
     const float vx = readlane_f(avc.x, rel), vy = readlane_f(avc.y, rel);
     const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
     // all steps of one window touch distinct cells: read them all, then add
     // and write, so the window costs one LDS round trip, not one per step
+    // (every window of a run has NK steps: S^2 > 64 (NK - 1))
     float2 cur[NK];
 #pragma unroll
-    for (int k = 0; k < NK; ++k)
-      if (k * 64 < S2) cur[k] = lds_load(lay.addr(base_b, k, park));
+    for (int k = 0; k < NK; ++k) cur[k] = lds_load(lay.addr(base_b, k, park));
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
-      if (k * 64 < S2) {
-        const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
-        cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
-        cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
-        cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
-        cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
-        lds_store(lay.addr(base_b, k, park), cur[k]);
-      }
+      const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+      cur[k].x = __builtin_fmaf(gx, vx, cur[k].x);
+      cur[k].x = __builtin_fmaf(gy, vy, cur[k].x);
+      cur[k].y = __builtin_fmaf(gx, vy, cur[k].y);
+      cur[k].y = __builtin_fmaf(-gy, vx, cur[k].y);
+      lds_store(lay.addr(base_b, k, park), cur[k]);
     }
   };
 #pragma unroll
