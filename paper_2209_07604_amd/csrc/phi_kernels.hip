@@ -608,6 +608,12 @@ struct TapLayout {
 #ifndef PHI_SCATTER_DEPTH_REGS
 #define PHI_SCATTER_DEPTH_REGS 16
 #endif
+// The one-pass dual step runs few waves per SIMD (its LDS holds a tile and
+// an accumulator per wave) and has registers to spare: it keeps more taps in
+// flight.
+#ifndef PHI_FUSED_DEPTH_REGS
+#define PHI_FUSED_DEPTH_REGS 16
+#endif
 template <int GP, int NK, int REGS>
 struct Depth {
   static constexpr int regs = GP == 0 ? REGS / 2 : REGS;
@@ -724,6 +730,30 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     return make_float2(__builtin_fmaf(th, sx, readlane_f(pre.x, rel)), __builtin_fmaf(th, sy, readlane_f(pre.y, rel)));
   };
   const uint32_t apark = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
+  // accumulator cells of a window, read ahead of its c (addresses kept for
+  // the write-back; the layout may change before then)
+  auto acc_cells = [&](uint32_t mt, float2(&A)[NK], uint32_t(&adr)[NK]) {
+    const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
+    if (S != lay.S) lay.set(S, P, lane);
+    const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      adr[k] = lay.addr(base_b, k, apark);
+      A[k] = lds_load(adr[k]);
+    }
+  };
+  auto scatter_to = [&](const R(&g)[NK], float2(&A)[NK], const uint32_t(&adr)[NK], float2 c) {
+    const float vx = th * c.x, vy = th * c.y;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
+      A[k].x = __builtin_fmaf(gx, vx, A[k].x);
+      A[k].x = __builtin_fmaf(gy, vy, A[k].x);
+      A[k].y = __builtin_fmaf(gx, vy, A[k].y);
+      A[k].y = __builtin_fmaf(-gy, vx, A[k].y);
+      lds_store(adr[k], A[k]);
+    }
+  };
   auto scatter = [&](const R(&g)[NK], uint32_t mt, float2 c) {
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     if (S != lay.S) lay.set(S, P, lane);
@@ -768,7 +798,29 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
 #pragma unroll
     for (int d = 0; d + 1 < D; d += 2) {
       float ax0, ay0, ax1, ay1;
-      if constexpr (NK <= 3) {  // both windows' cell reads in flight together
+      if constexpr (MODE == 2 && NK <= 3) {
+        // The first window's accumulator cells are read with the grid cells
+        // (the previous pair's writes precede them in the wave's LDS order);
+        // the second window's are read after the first's write-back, since
+        // the two may share cells.
+        float2 X0[NK], X1[NK], A0[NK];
+        uint32_t adr0[NK];
+        cells(ms[d], X0);
+        acc_cells(ms[d], A0, adr0);
+        cells(ms[d + 1], X1);
+        dot(gb[d], X0, ax0, ay0);
+        settle(ax0, ay0);
+        dot(gb[d + 1], X1, ax1, ay1);
+        settle(ax1, ay1);
+        const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
+        place(rel0 + d, s.x, s.y);
+        scatter_to(gb[d], A0, adr0, cval(rel0 + d, s.x, s.y));
+        gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
+        place(rel0 + d + 1, s.z, s.w);
+        scatter(gb[d + 1], ms[d + 1], cval(rel0 + d + 1, s.z, s.w));
+        gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
+        continue;
+      } else if constexpr (NK <= 3) {  // both windows' cell reads in flight together
         float2 X0[NK], X1[NK];
         cells(ms[d], X0);
         cells(ms[d + 1], X1);
@@ -879,8 +931,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
 #define PHI_G_CASE(K)                                                                                  \
   case K:                                                                                              \
     if constexpr (K <= NKM)                                                                            \
-      wtap = gather_item<GP, MODE, K, Depth<GP, K, PHI_GATHER_DEPTH_REGS>::value>(a, item, r0, r1, wtap, \
-                                                                                  vis, yv, rho2, res2, tile, ab); \
+      wtap = gather_item<GP, MODE, K, Depth<GP, K, MODE == 2 ? PHI_FUSED_DEPTH_REGS : PHI_GATHER_DEPTH_REGS>::value>( \
+          a, item, r0, r1, wtap, vis, yv, rho2, res2, tile, ab);                                      \
     break;
         PHI_G_CASE(1)
         PHI_G_CASE(2)
