@@ -462,7 +462,8 @@ def main():
         p.set_timing(False)
         stages, calls = p.get_timing()
         info = info_t = p.info()
-        results[form] = dict(ms_per_step=ms, tile=info_t["tile"], persist_blocks=info_t["persist_blocks"], wall_ms_per_step=1e3 * wall / args.steps,
+        results[form] = dict(ms_per_step=ms, tile=info_t["tile"], persist_blocks=info_t["persist_blocks"],
+                             one_pass=bool(fused), wall_ms_per_step=1e3 * wall / args.steps,
                              vis_per_s=M / (ms * 1e-3),
                              alg_GBs=info["alg_bytes_dual_step"] / (ms * 1e-3) / 1e9,
                              stage_ms={k_: v_ / max(calls, 1) for k_, v_ in stages.items()},
@@ -490,7 +491,9 @@ def main():
         del src, dst
     head = "batched_f16" if "batched_f16" in results else forms[-1]
     hp = plans[head.split("_")[1]]
-    hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0))
+    # the headline form's launch settings (a later form may have changed the plan's flags)
+    hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0) |
+                 (FUSED_GH if results[head]["one_pass"] else 0))
     log("[bench] %s: forward, adjoint and PDFB iterations" % head)
     extras = time_extras(hp, x, xt, hp.to_plan(v_init), y_plan[head.split("_")[1]], eps, args.steps, args.warmup,
                          dev)
