@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdint>
@@ -98,6 +99,10 @@ struct WorkList {
   std::vector<int32_t> tile_ptr;
   std::vector<TileEntry> entries;
   std::vector<int32_t> chan_item0;          // [L + 1]
+  // the items again, by pitch (largest first), for launches whose LDS is
+  // sized per pitch; runs of equal pitch as (pitch, first, end)
+  std::vector<Item> items_by_pitch;
+  std::vector<std::array<int32_t, 3>> pitch_runs;
 };
 
 struct phi_plan_s {
@@ -120,7 +125,8 @@ struct phi_plan_s {
   WorkList& W() { return cands[cur]; }
   const WorkList& W() const { return cands[cur]; }
   // workspace layout
-  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_binfo = 0, off_tptr = 0, off_ent = 0,
+  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_items_p = 0, off_binfo = 0,
+         off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
          off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0;
   char* ws = nullptr;
@@ -282,6 +288,7 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
       it.poff = poff;
       poff += (int64_t)it.pitch * it.pitch;
       max_pitch = std::max(max_pitch, it.pitch);
+      it.slot = (int32_t)w.items.size();
       w.items.push_back(it);
     }
     bi.item1 = (int32_t)w.items.size();
@@ -290,6 +297,47 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   }
   w.partial_elems = poff;
   w.max_pitch = std::max(max_pitch, T);
+  // Pitch classes for the one-pass dual step, each launched with the LDS of
+  // its largest pitch.  Pitches are grouped from the smallest up until a
+  // class holds a few rounds of work-groups over the whole chip (a smaller
+  // launch would be mostly tail); an undersized top class joins the one
+  // below.  Inside a class the items run largest first, so the short ones
+  // fill the launch's tail.
+  {
+    constexpr int kMaxP = 256;
+    constexpr int64_t kMinClassItems = 8 * 256 * 4;  // ~4 rounds of 8 groups on 256 CUs
+    std::vector<int64_t> count(kMaxP, 0);
+    for (const Item& it : w.items) ++count[std::min(it.pitch, kMaxP - 1)];
+    std::vector<int> class_of(kMaxP, -1);
+    std::vector<std::pair<int, int64_t>> classes;  // (pitch of the launch, items)
+    std::vector<int> members;
+    for (int P = 0; P < kMaxP; ++P) {
+      if (!count[P]) continue;
+      if (classes.empty() || classes.back().second >= kMinClassItems) classes.push_back({P, 0});
+      classes.back().first = P;
+      classes.back().second += count[P];
+      class_of[P] = (int)classes.size() - 1;
+    }
+    if (classes.size() > 1 && classes.back().second < kMinClassItems) {
+      const int top = (int)classes.size() - 1;
+      classes[top - 1].first = classes[top].first;
+      for (int P = 0; P < kMaxP; ++P)
+        if (class_of[P] == top) class_of[P] = top - 1;
+      classes.pop_back();
+    }
+    auto cls = [&](const Item& it) { return class_of[std::min(it.pitch, kMaxP - 1)]; };
+    w.items_by_pitch = w.items;
+    std::stable_sort(w.items_by_pitch.begin(), w.items_by_pitch.end(), [&](const Item& x, const Item& y) {
+      return cls(x) != cls(y) ? cls(x) > cls(y) : x.ntap > y.ntap;
+    });
+    for (int32_t i = 0; i < (int32_t)w.items_by_pitch.size();) {
+      const int c = cls(w.items_by_pitch[i]);
+      int32_t j = i;
+      while (j < (int32_t)w.items_by_pitch.size() && cls(w.items_by_pitch[j]) == c) ++j;
+      w.pitch_runs.push_back({classes[c].first, i, j});
+      i = j;
+    }
+  }
   // channel item ranges (blocks are channel-major)
   for (int b = 0; b < p->nblk; ++b) w.chan_item0[p->blk_chan[b] + 1] = w.binfo[b].item1;
   for (int l = 0; l < p->L; ++l) w.chan_item0[l + 1] = std::max(w.chan_item0[l + 1], w.chan_item0[l]);
@@ -340,6 +388,7 @@ static void layout(phi_plan_s* p) {
     n_part = std::max(n_part, (size_t)w.partial_elems);
   }
   p->off_items = take(n_items * sizeof(Item));
+  p->off_items_p = take(n_items * sizeof(Item));
   p->off_binfo = take((size_t)p->nblk * sizeof(BlockInfo));
   p->off_tptr = take(n_tptr * 4);
   p->off_ent = take(n_items * sizeof(TileEntry));
@@ -367,6 +416,7 @@ static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
     if (e == hipSuccess && n) e = hipMemcpyAsync(p->ws + off, src, n, hipMemcpyHostToDevice, s);
   };
   up(p->off_items, w.items.data(), w.items.size() * sizeof(Item));
+  up(p->off_items_p, w.items_by_pitch.data(), w.items_by_pitch.size() * sizeof(Item));
   up(p->off_binfo, w.binfo.data(), w.binfo.size() * sizeof(BlockInfo));
   up(p->off_tptr, w.tile_ptr.data(), w.tile_ptr.size() * 4);
   up(p->off_ent, w.entries.data(), w.entries.size() * sizeof(TileEntry));
@@ -860,6 +910,24 @@ struct Runner {
     });
     adj_fft(x, l0, l1);
   }
+  // The one-pass dual step's gather (mode 2).  Over all channels it runs
+  // once per item pitch, on the items sorted by pitch, each launch with the
+  // LDS of its pitch: items with smaller windows then fit more work-groups
+  // per compute unit.  A channel range runs its own items in one launch.
+  hipError_t dual_gs(const GArgs& a, float2* v, const float2* y, int l0, int l1) {
+    double* norms = p->at<double>(p->off_norms);
+    if (l0 == 0 && l1 == p->L) {
+      GArgs b = a;
+      b.items = p->at<Item>(p->off_items_p);
+      for (const auto& r : p->W().pitch_runs) {
+        const hipError_t e = launch_gather(p->gprec, 2, b, v, y, norms, r[0], r[1], r[2], persist_blocks(), s);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+    return launch_gather(p->gprec, 2, a, v, y, norms, p->W().max_pitch, p->W().chan_item0[l0],
+                         p->W().chan_item0[l1], persist_blocks(), s);
+  }
   void dual(const float* xt, float2* v, const float2* y, const double* eps, const double* sigma, float* grad,
             double* rho, double* res, int l0, int l1) {
     fwd_fft(xt, l0, l1);
@@ -870,10 +938,7 @@ struct Runner {
     if (p->fused()) {
       // c and G^H theta c in one pass over G; the per-block factor
       // sigma * scale goes into v+ and the merge once the norms are known
-      stage(10, [&] {
-        return launch_gather(p->gprec, 2, a, v, y, p->at<double>(p->off_norms), p->W().max_pitch, it0, it1,
-                             persist_blocks(), s);
-      });
+      stage(10, [&] { return dual_gs(a, v, y, l0, l1); });
       stage(3, [&] {
         return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),
                                p->at<double>(p->off_bpart), eps, rho, res, p->at<double>(p->off_scale),
@@ -1096,9 +1161,7 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
     auto once = [&] {
       const GArgs a = r.gargs();
       const int n = (int)p->W().items.size();
-      if (fused && r.err == hipSuccess)
-        r.err = launch_gather(p->gprec, 2, a, vs, vs, p->at<double>(p->off_norms), p->W().max_pitch, 0, n,
-                              r.persist_blocks(), s);
+      if (fused && r.err == hipSuccess) r.err = r.dual_gs(a, vs, vs, 0, p->L);
       if (!fused && g && r.err == hipSuccess)
         r.err = launch_gather(p->gprec, 0, a, vs, nullptr, nullptr, p->W().max_pitch, 0, n, r.persist_blocks(), s);
       if (!fused && sc && r.err == hipSuccess)

@@ -30,7 +30,7 @@ struct Item {
   int32_t pitch;
   int32_t ntap;    // taps of the run (sum of S^2)
   int32_t sub[3];  // taps before visibility wv[w - 1], w = 1..3
-  int32_t pad;
+  int32_t slot;    // the item's index in plan order (its norm slot)
   int32_t wv[3];   // plan-order visibility where the gather's wave w = 1..3
                    // starts (W <= 4 waves; equal shares of S^2 + 64 per window)
   int32_t pad2;

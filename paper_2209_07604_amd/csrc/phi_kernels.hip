@@ -961,8 +961,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
           r0 += s_norm[2 * k];
           r1 += s_norm[2 * k + 1];
         }
-        item_norms[2 * (int64_t)it] = r0;
-        item_norms[2 * (int64_t)it + 1] = r1;
+        item_norms[2 * (int64_t)item.slot] = r0;
+        item_norms[2 * (int64_t)item.slot + 1] = r1;
       }
     }
     if (MODE == 2) {  // the item's partial: the waves' accumulators in a fixed order
