@@ -893,40 +893,47 @@ struct Runner {
                                p->at<float>(p->off_sx), p->at<float2>(p->off_twx), p->Ny, p->Nx, l0, nl, s);
     });
   }
-  void forward(const float* x, float2* y, int l0, int l1) {
-    fwd_fft(x, l0, l1);
-    const GArgs a = gargs();
-    stage(2, [&] {
-      return launch_gather(p->gprec, 0, a, y, nullptr, nullptr, p->W().max_pitch, p->W().chan_item0[l0],
-                           p->W().chan_item0[l1],
-                           persist_blocks(), s);
-    });
-  }
-  void adjoint(const float2* v, float* x, int l0, int l1) {
-    const GArgs a = gargs();
-    stage(4, [&] {
-      return launch_scatter(p->gprec, 0, a, const_cast<float2*>(v), p->at<float2>(p->off_part), p->W().max_pitch,
-                            p->W().chan_item0[l0], p->W().chan_item0[l1], persist_blocks(), s);
-    });
-    adj_fft(x, l0, l1);
-  }
-  // The one-pass dual step's gather (mode 2).  Over all channels it runs
-  // once per item pitch, on the items sorted by pitch, each launch with the
-  // LDS of its pitch: items with smaller windows then fit more work-groups
-  // per compute unit.  A channel range runs its own items in one launch.
-  hipError_t dual_gs(const GArgs& a, float2* v, const float2* y, int l0, int l1) {
-    double* norms = p->at<double>(p->off_norms);
-    if (l0 == 0 && l1 == p->L) {
+  // A G stage over channels [l0, l1).  The one-pass dual step (by_pitch)
+  // over all channels runs once per pitch class, on the items grouped by
+  // pitch with the largest first, each launch with the LDS of its class: its
+  // occupancy is set by LDS, so items with smaller windows fit more
+  // work-groups per compute unit, and short items fill each launch's tail.
+  // Everything else runs its items in plan order in one launch (the two-pass
+  // kernels measured slower by pitch class: they gain no occupancy and lose
+  // the locality of neighbouring items).  launch(args, pitch, first, end).
+  template <typename F>
+  hipError_t g_stage(const GArgs& a, int l0, int l1, bool by_pitch, F&& launch) {
+    if (by_pitch && l0 == 0 && l1 == p->L && p->gprec != PHI_G_KB) {
       GArgs b = a;
       b.items = p->at<Item>(p->off_items_p);
       for (const auto& r : p->W().pitch_runs) {
-        const hipError_t e = launch_gather(p->gprec, 2, b, v, y, norms, r[0], r[1], r[2], persist_blocks(), s);
+        const hipError_t e = launch(b, r[0], r[1], r[2]);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     }
-    return launch_gather(p->gprec, 2, a, v, y, norms, p->W().max_pitch, p->W().chan_item0[l0],
-                         p->W().chan_item0[l1], persist_blocks(), s);
+    return launch(a, p->W().max_pitch, p->W().chan_item0[l0], p->W().chan_item0[l1]);
+  }
+  hipError_t gather(int mode, const GArgs& a, float2* v, const float2* y, int l0, int l1) {
+    double* norms = mode ? p->at<double>(p->off_norms) : nullptr;
+    return g_stage(a, l0, l1, mode == 2, [&](const GArgs& b, int P, int i0, int i1) {
+      return launch_gather(p->gprec, mode, b, v, y, norms, P, i0, i1, persist_blocks(), s);
+    });
+  }
+  hipError_t scatter(int mode, const GArgs& a, float2* v, int l0, int l1) {
+    return g_stage(a, l0, l1, false, [&](const GArgs& b, int P, int i0, int i1) {
+      return launch_scatter(p->gprec, mode, b, v, p->at<float2>(p->off_part), P, i0, i1, persist_blocks(), s);
+    });
+  }
+  void forward(const float* x, float2* y, int l0, int l1) {
+    fwd_fft(x, l0, l1);
+    const GArgs a = gargs();
+    stage(2, [&] { return gather(0, a, y, nullptr, l0, l1); });
+  }
+  void adjoint(const float2* v, float* x, int l0, int l1) {
+    const GArgs a = gargs();
+    stage(4, [&] { return scatter(0, a, const_cast<float2*>(v), l0, l1); });
+    adj_fft(x, l0, l1);
   }
   void dual(const float* xt, float2* v, const float2* y, const double* eps, const double* sigma, float* grad,
             double* rho, double* res, int l0, int l1) {
@@ -938,7 +945,7 @@ struct Runner {
     if (p->fused()) {
       // c and G^H theta c in one pass over G; the per-block factor
       // sigma * scale goes into v+ and the merge once the norms are known
-      stage(10, [&] { return dual_gs(a, v, y, l0, l1); });
+      stage(10, [&] { return gather(2, a, v, y, l0, l1); });
       stage(3, [&] {
         return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),
                                p->at<double>(p->off_bpart), eps, rho, res, p->at<double>(p->off_scale),
@@ -948,19 +955,13 @@ struct Runner {
       adj_fft(grad, l0, l1, sigma, p->at<double>(p->off_scale));
       return;
     }
-    stage(2, [&] {
-      return launch_gather(p->gprec, 1, a, v, y, p->at<double>(p->off_norms), p->W().max_pitch, it0, it1,
-                           persist_blocks(), s);
-    });
+    stage(2, [&] { return gather(1, a, v, y, l0, l1); });
     stage(3, [&] {
       return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),
                              p->at<double>(p->off_bpart), eps, rho, res,
                              p->at<double>(p->off_scale), p->at<int>(p->off_flag), b0, b1 - b0, s);
     });
-    stage(4, [&] {
-      return launch_scatter(p->gprec, 1, a, v, p->at<float2>(p->off_part), p->W().max_pitch, it0, it1,
-                            persist_blocks(), s);
-    });
+    stage(4, [&] { return scatter(1, a, v, l0, l1); });
     adj_fft(grad, l0, l1);
   }
 };
@@ -1160,13 +1161,9 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
     Runner r{p, s, false};
     auto once = [&] {
       const GArgs a = r.gargs();
-      const int n = (int)p->W().items.size();
-      if (fused && r.err == hipSuccess) r.err = r.dual_gs(a, vs, vs, 0, p->L);
-      if (!fused && g && r.err == hipSuccess)
-        r.err = launch_gather(p->gprec, 0, a, vs, nullptr, nullptr, p->W().max_pitch, 0, n, r.persist_blocks(), s);
-      if (!fused && sc && r.err == hipSuccess)
-        r.err = launch_scatter(p->gprec, 0, a, vs, p->at<float2>(p->off_part), p->W().max_pitch, 0,
-                               n, r.persist_blocks(), s);
+      if (fused && r.err == hipSuccess) r.err = r.gather(2, a, vs, vs, 0, p->L);
+      if (!fused && g && r.err == hipSuccess) r.err = r.gather(0, a, vs, nullptr, 0, p->L);
+      if (!fused && sc && r.err == hipSuccess) r.err = r.scatter(0, a, vs, 0, p->L);
       if ((sc || fused) && r.err == hipSuccess)
         r.err = launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
                              p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, 0, p->L, nullptr,
