@@ -898,26 +898,97 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
   extern __shared__ float2 tile[];  // P*P cells, a zero cell, then the wave norms
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
-    const Item item = a.items[it];
+  constexpr int kThreads = 64 * kGatherWaves;
+  // One-pass mode (LDS sets its occupancy, so registers are spare): the next
+  // item's grid region is loaded into registers while the current item runs
+  // (its loads travel with the first G fetches, which an item waits for
+  // anyway), so an item starts with LDS writes instead of a memory round
+  // trip.  Item descriptors come two items ahead as one dword per lane,
+  // read with readlane, so no scalar load is waited for either.  Regions
+  // beyond kPre cells per thread (pitch above 32) are copied at the start.
+  constexpr int kPre = MODE == 2 ? 1024 / kThreads : 1;
+  constexpr int kWords = (int)(sizeof(Item) / 4);
+  const int G = gridDim.x;
+  auto cell = [&](int chan, int ty0, int tx0, int P, int e) {  // cell e of a region (rows ty0.., wrapped)
+    const int r = e / P, c = e - (e / P) * P;
+    int gr = ty0 + r, gc = tx0 + c;
+    gr -= (gr >= a.Ky) ? a.Ky : 0;
+    gc -= (gc >= a.Kx) ? a.Kx : 0;
+    return a.grid[((size_t)chan * a.Ky + gr) * a.Kx + gc];
+  };
+  auto desc = [&](int i) -> int {
+    return (i < it1 && lane < kWords) ? reinterpret_cast<const int*>(a.items + i)[lane] : 0;
+  };
+  auto field = [](int d, int k) { return __builtin_amdgcn_readlane(d, k); };
+  static_assert(offsetof(Item, tap0) == 0 && offsetof(Item, poff) == 8 && offsetof(Item, v0) == 16 &&
+                    offsetof(Item, blk) == 24 && offsetof(Item, chan) == 28 && offsetof(Item, ty0) == 32 &&
+                    offsetof(Item, tx0) == 36 && offsetof(Item, pitch) == 40 && offsetof(Item, sub) == 48 &&
+                    offsetof(Item, slot) == 60 && offsetof(Item, wv) == 64 && sizeof(Item) == 80,
+                "descriptor words");
+  auto unpack = [&](int d) {
+    Item t;
+    t.tap0 = (int64_t)(((uint64_t)(uint32_t)field(d, 1) << 32) | (uint32_t)field(d, 0));
+    t.poff = (int64_t)(((uint64_t)(uint32_t)field(d, 3) << 32) | (uint32_t)field(d, 2));
+    t.v0 = field(d, 4);
+    t.v1 = field(d, 5);
+    t.blk = field(d, 6);
+    t.chan = field(d, 7);
+    t.ty0 = field(d, 8);
+    t.tx0 = field(d, 9);
+    t.pitch = field(d, 10);
+    t.ntap = field(d, 11);
+    t.sub[0] = field(d, 12);
+    t.sub[1] = field(d, 13);
+    t.sub[2] = field(d, 14);
+    t.slot = field(d, 15);
+    t.wv[0] = field(d, 16);
+    t.wv[1] = field(d, 17);
+    t.wv[2] = field(d, 18);
+    t.pad2 = 0;
+    return t;
+  };
+  float2 pre[kPre];
+  auto prefetch = [&](int d) {
+    const int chan = field(d, 7), ty0 = field(d, 8), tx0 = field(d, 9), P = field(d, 10);
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) {
+      const int e = tid + q * kThreads;
+      pre[q] = e < P * P ? cell(chan, ty0, tx0, P, e) : make_float2(0.f, 0.f);
+    }
+  };
+  int it = it0 + blockIdx.x;
+  int d0 = 0, d1 = 0;
+  if constexpr (MODE == 2) {
+    d0 = desc(it);
+    d1 = desc(it + G);
+    if (it < it1) prefetch(d0);
+  }
+  for (; it < it1; it += G) {
+    const Item item = MODE == 2 ? unpack(d0) : a.items[it];
     const int P = item.pitch;
     double* s_norm = reinterpret_cast<double*>(tile + P * P + 1);
-    // copy the item's grid region (rows ty0.., columns tx0.., wrapped)
-    const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
-    for (int e = tid; e < P * P; e += 64 * kGatherWaves) {
-      const int r = e / P, c = e - (e / P) * P;
-      int gr = item.ty0 + r, gc = item.tx0 + c;
-      gr -= (gr >= a.Ky) ? a.Ky : 0;
-      gc -= (gc >= a.Kx) ? a.Kx : 0;
-      tile[e] = grid[(size_t)gr * a.Kx + gc];
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int q = 0; q < kPre; ++q) {
+        const int e = tid + q * kThreads;
+        if (e < P * P) tile[e] = pre[q];
+      }
+      for (int e = tid + kPre * kThreads; e < P * P; e += kThreads) tile[e] = cell(item.chan, item.ty0, item.tx0, P, e);
+    } else {
+      for (int e = tid; e < P * P; e += kThreads) tile[e] = cell(item.chan, item.ty0, item.tx0, P, e);
     }
     if (tid == 0) tile[P * P] = make_float2(0.f, 0.f);  // the zero cell
     // MODE 2: one accumulator per wave (P*P cells and 64 spare cells) behind
     // the tile, its zero cell and the norms
     const int acells = P * P + 64, a0 = P * P + 16;
     if (MODE == 2)
-      for (int e = tid; e < kGatherWaves * acells; e += 64 * kGatherWaves) tile[a0 + e] = make_float2(0.f, 0.f);
+      for (int e = tid; e < kGatherWaves * acells; e += kThreads) tile[a0 + e] = make_float2(0.f, 0.f);
     __syncthreads();
+    int d2 = 0;
+    if constexpr (MODE == 2) {  // the next item's region and the descriptor after it
+      d2 = desc(it + 2 * G);
+      if (it + G < it1) prefetch(d1);
+    }
     const uint32_t ab = lds_offset(tile) + (uint32_t)(a0 + w * acells) * 8u;
     // (selects, not indexing: a run-time index would move the item to scratch)
     const int wv0 = w == 0 ? item.v0 : w == 1 ? item.wv[0] : w == 2 ? item.wv[1] : item.wv[2];
@@ -978,6 +1049,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
       }
     }
     __syncthreads();
+    d0 = d1;
+    d1 = d2;
   }
 }
 
