@@ -1458,7 +1458,27 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
     const int r = e / T, c = e % T;
     float sx = 0.f, sy = 0.f;
     if (n <= kMergeList) {
-      for (int k = 0; k < n; ++k) {
+      // four entries at a time, loads first: an entry that does not cover
+      // this cell reads its partial's first cell and adds it with weight 0
+      // (the sum keeps its order; partial cells are finite)
+      int k = 0;
+      for (; k + 4 <= n; k += 4) {
+        float2 v[4];
+        float f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ly = r + s_oy[k + u], lx = c + s_ox[k + u], P = s_pitch[k + u];
+          const bool in = ly < P && lx < P;
+          f[u] = in ? s_fac[k + u] : 0.f;
+          v[u] = partials[s_off[k + u] + (in ? (int64_t)ly * P + lx : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          sx = __builtin_fmaf(f[u], v[u].x, sx);
+          sy = __builtin_fmaf(f[u], v[u].y, sy);
+        }
+      }
+      for (; k < n; ++k) {
         const int ly = r + s_oy[k], lx = c + s_ox[k], P = s_pitch[k];
         if (ly < P && lx < P) {
           const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
