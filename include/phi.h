@@ -141,6 +141,13 @@ typedef struct {
                                   work-group per item)                       */
   int32_t fused;               /* 1 if the dual step runs in one pass over G
                                   (PHI_FUSED_GH set and usable)              */
+  int32_t pitch_classes;       /* launches of the one-pass step over all
+                                  channels: items grouped by tile pitch, each
+                                  group with LDS sized for its pitch, largest
+                                  items first.  Pitches are grouped from the
+                                  smallest up until a group holds 8192 items
+                                  (environment PHI_PITCH_CLASS_ITEMS, read at
+                                  phi_plan_create, overrides; >= 1)          */
 } phi_info;
 
 /* Validate `desc`, sort visibilities and build the work lists (host only,

@@ -58,7 +58,7 @@ class Info(ctypes.Structure):
         ("alg_bytes_gather", ctypes.c_double), ("alg_bytes_scatter", ctypes.c_double),
         ("ky", ctypes.c_int32), ("kx", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
-        ("fused", ctypes.c_int32),
+        ("fused", ctypes.c_int32), ("pitch_classes", ctypes.c_int32),
     ]
 
 

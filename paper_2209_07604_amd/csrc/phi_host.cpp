@@ -12,6 +12,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -305,7 +306,11 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   // fill the launch's tail.
   {
     constexpr int kMaxP = 256;
-    constexpr int64_t kMinClassItems = 8 * 256 * 4;  // ~4 rounds of 8 groups on 256 CUs
+    int64_t kMinClassItems = 8 * 256 * 4;  // ~4 rounds of 8 groups on 256 CUs
+    if (const char* env = std::getenv("PHI_PITCH_CLASS_ITEMS")) {
+      const long v = std::strtol(env, nullptr, 10);
+      if (v >= 1) kMinClassItems = v;
+    }
     std::vector<int64_t> count(kMaxP, 0);
     for (const Item& it : w.items) ++count[std::min(it.pitch, kMaxP - 1)];
     std::vector<int> class_of(kMaxP, -1);
@@ -594,6 +599,7 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->n_stages = kNumStages;
   info->persist_blocks = (p->flags & PHI_PERSISTENT) ? p->persist : 0;
   info->fused = p->fused() ? 1 : 0;
+  info->pitch_classes = (int32_t)p->W().pitch_runs.size();
   return PHI_OK;
 }
 

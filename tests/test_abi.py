@@ -175,3 +175,29 @@ def test_kaiser_bessel_mode_checks():
     assert lib.phi_plan_load_kb(h, 0, ctypes.c_void_p(16), None) == -8   # not bound yet
     assert lib.phi_plan_load_kb(h, 3, ctypes.c_void_p(16), None) == -3
     assert lib.phi_plan_destroy(h) == 0
+
+
+def test_pitch_classes(monkeypatch):
+    """The one-pass dual step launches once per group of item pitches (host
+    logic, no GPU): pitches are grouped from the smallest up until a group
+    holds PHI_PITCH_CLASS_ITEMS items (default 8192).  Three items in three
+    tiles with windows 1, 7 and 21 have pitches 32, 38 and 52 at T = 32."""
+    L, lib = _lib()
+    kw = dict(n_blocks=(1,), n_vis=(3,), S=[1, 7, 21], base=[[0, 0], [40, 40], [5, 50]], theta=[1.0])
+
+    def classes():
+        d, keep = _desc(L, **kw)
+        h = ctypes.c_void_p()
+        assert lib.phi_plan_create(ctypes.byref(d), ctypes.byref(h)) == 0
+        info = L.Info()
+        assert lib.phi_plan_get_info(h, ctypes.byref(info)) == 0
+        assert info.n_items == 3
+        lib.phi_plan_destroy(h)
+        return info.pitch_classes
+
+    monkeypatch.delenv("PHI_PITCH_CLASS_ITEMS", raising=False)
+    assert classes() == 1
+    monkeypatch.setenv("PHI_PITCH_CLASS_ITEMS", "1")
+    assert classes() == 3
+    monkeypatch.setenv("PHI_PITCH_CLASS_ITEMS", "2")   # 32 + 38 close a group; 52 alone joins it
+    assert classes() == 1

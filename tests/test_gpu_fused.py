@@ -66,3 +66,38 @@ def test_fused_matches_separate_and_oracle(name, prec):
         e = rel_l2(grad_f[l], grad_o[l])
         _say("  grad ch", l, "vs oracle", e, "vs separate", rel_l2(grad_f[l], grad_s[l]))
         assert e <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["f16", "c64"])
+def test_fused_over_pitch_classes(prec, monkeypatch):
+    """The one-pass step over all channels runs once per pitch class on the
+    items regrouped by pitch, largest first.  Forced to one class per pitch,
+    it must still give v+ bitwise equal to the two passes, equal norms, and
+    grad within the bound of the oracle."""
+    from test_gpu_parity import gpu_dual
+    from paper_2209_07604_amd import FUSED_GH
+    import oracle
+    monkeypatch.setenv("PHI_PITCH_CLASS_ITEMS", "1")
+    c = case("C2s")
+    plan = c.plan(g_prec=prec)           # the variable is read when the plan is created
+    plan.set_tuning(16, 0)
+    plan.set_flags(FUSED_GH)
+    info = plan.info()
+    _say("[fused classes]", prec, "pitch classes", info["pitch_classes"])
+    assert info["fused"] == 1 and info["pitch_classes"] > 1
+    nb = len(c.blocks)
+    sigma = np.linspace(0.9, 1.1, nb)
+    Vp_f, grad_f, rho_f, res_f = gpu_dual(c, plan, c.V, c.eps, sigma)
+    plan.set_flags(0)
+    Vp_s, grad_s, rho_s, res_s = gpu_dual(c, plan, c.V, c.eps, sigma)
+    assert all(np.array_equal(x, y) for x, y in zip(Vp_f, Vp_s))
+    assert np.array_equal(rho_f, rho_s) and np.array_equal(res_f, res_s)
+    op = c.op if prec == "c64" else c.operator(c.theta, prec=prec)
+    _, grad_o, rho_o, _ = oracle.dual_step(op, {l: x.astype(np.float64) for l, x in c.Xt.items()},
+                                           c.V, c.Y, c.eps, sigma)
+    assert rel_l2(rho_f, rho_o) <= 1e-5
+    for l in range(c.prob.L):
+        e = rel_l2(grad_f[l], grad_o[l])
+        _say("  grad ch", l, "vs oracle", e)
+        assert e <= 1e-5
+
