@@ -946,7 +946,6 @@ struct Runner {
     fwd_fft(xt, l0, l1);
     GArgs a = gargs();
     a.sigma = sigma;
-    const int it0 = p->W().chan_item0[l0], it1 = p->W().chan_item0[l1];
     const int b0 = p->chan_blk0[l0], b1 = p->chan_blk0[l1];
     if (p->fused()) {
       // c and G^H theta c in one pass over G; the per-block factor
@@ -957,7 +956,9 @@ struct Runner {
                                p->at<double>(p->off_bpart), eps, rho, res, p->at<double>(p->off_scale),
                                p->at<int>(p->off_flag), b0, b1 - b0, s);
       });
-      stage(11, [&] { return launch_vscale(a.items, v, sigma, p->at<double>(p->off_scale), it0, it1, s); });
+      stage(11, [&] {
+        return launch_vscale(p->at<BlockInfo>(p->off_binfo), v, sigma, p->at<double>(p->off_scale), b0, b1 - b0, s);
+      });
       adj_fft(grad, l0, l1, sigma, p->at<double>(p->off_scale));
       return;
     }

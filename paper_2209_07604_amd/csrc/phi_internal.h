@@ -93,8 +93,8 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
 // needs for the largest pitch; 0 if it does not fit a work-group.
 size_t fused_lds_bytes(int max_pitch);
 // v <- sigma_b * scale_b * v over the visibilities of items [it0, it1)
-hipError_t launch_vscale(const Item* items, float2* vis, const double* sigma, const double* scale, int it0, int it1,
-                         hipStream_t s);
+hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sigma, const double* scale, int b0,
+                         int nb, hipStream_t s);
 // mode: 0 adjoint (read v), 1 dual (v+ = sigma*scale*c, written back)
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
                           int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);

@@ -1884,13 +1884,16 @@ __global__ __launch_bounds__(64) void k_build_g(BuildArgs a, int it0) {
   }
 }
 
-// v+ = sigma_b scale_b c over the visibilities of each item (fused dual step)
-__global__ __launch_bounds__(256) void k_vscale(const Item* __restrict__ items, float2* __restrict__ vis,
+// v+ = sigma_b scale_b c over each block's visibilities (fused dual step; a
+// block is one plan-order range): kVscaleChunks work-groups per block stream it
+constexpr int kVscaleChunks = 64;
+__global__ __launch_bounds__(256) void k_vscale(const BlockInfo* __restrict__ blocks, float2* __restrict__ vis,
                                                 const double* __restrict__ sigma, const double* __restrict__ scale,
-                                                int it0) {
-  const Item item = items[it0 + blockIdx.x];
-  const float f = (float)((sigma ? sigma[item.blk] : 1.0) * scale[item.blk]);
-  for (int v = item.v0 + threadIdx.x; v < item.v1; v += 256) {
+                                                int b0) {
+  const int b = b0 + blockIdx.y;
+  const BlockInfo bi = blocks[b];
+  const float f = (float)((sigma ? sigma[b] : 1.0) * scale[b]);
+  for (int64_t v = bi.v0 + (int64_t)blockIdx.x * 256 + threadIdx.x; v < bi.v1; v += (int64_t)kVscaleChunks * 256) {
     const float2 c = vis[v];
     vis[v] = make_float2(f * c.x, f * c.y);
   }
@@ -2258,10 +2261,10 @@ hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_vscale(const Item* items, float2* vis, const double* sigma, const double* scale, int it0, int it1,
-                         hipStream_t s) {
-  if (it1 <= it0) return hipSuccess;
-  hipLaunchKernelGGL(k_vscale, dim3(it1 - it0), dim3(256), 0, s, items, vis, sigma, scale, it0);
+hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sigma, const double* scale, int b0,
+                         int nb, hipStream_t s) {
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vscale, dim3(kVscaleChunks, nb), dim3(256), 0, s, blocks, vis, sigma, scale, b0);
   return hipGetLastError();
 }
 
