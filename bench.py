@@ -536,7 +536,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": dur * 1e3, "stream_copy_GBs": copy_gbs,
+                     "avg_launch_ms": dur * 1e3,
+                     # the one-pass stage is one launch per pitch class; its bytes
+                     # and time are per step (the sum over those launches)
+                     "launches_per_step": info["pitch_classes"] if dom == "dual_gs" else 1,
+                     "stream_copy_GBs": copy_gbs,
                      "frac_of_stream_copy": achieved / copy_gbs if copy_gbs else None},
         "forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
         "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
