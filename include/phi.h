@@ -282,13 +282,13 @@ phi_status phi_plan_set_timing(phi_plan plan, int32_t enable);
 phi_status phi_plan_get_timing(phi_plan plan, int32_t max_stages, double* ms,
                                const char** names, int32_t* n_stages, int64_t* n_calls);
 
-/* Time the candidate tile edges (16, 32, 64, where they divide the grid) and
+/* Time the candidate tile edges (16, 32, 64, where they divide the grid),
  * G-stage launch shapes (one work-group per item, or a persistent grid of 4
- * work-groups per compute unit) on the bound plan with its loaded G: `reps`
- * rounds of gather + scatter + merge on scratch vectors inside the
- * workspace.  Keeps the fastest; then, with stored G where it fits, times
- * the one-pass dual step against the two passes and sets or clears
- * PHI_FUSED_GH accordingly.  Overwrites the grid buffers.  Synchronous. */
+ * work-groups per compute unit) and, with stored G where its LDS fits, the
+ * one-pass dual step against the two passes, on the bound plan with its
+ * loaded G: `reps` rounds of the G stages + merge on scratch vectors inside
+ * the workspace.  Keeps the fastest combination (sets or clears
+ * PHI_FUSED_GH).  Overwrites the grid buffers.  Synchronous. */
 phi_status phi_plan_autotune(phi_plan plan, void* stream, int32_t reps);
 
 /* ---------------------------------------------------------------------------

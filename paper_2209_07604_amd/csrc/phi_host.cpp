@@ -1188,43 +1188,42 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
   };
   double best = 1e30;
   int best_c = p->cur, best_p = 0;
+  bool best_one = false;
   phi_status rc = PHI_OK;
-  // 1) tile edge x launch shape, both stages
+  // tile edge x launch shape x (two passes, or one pass where its LDS fits):
+  // the fastest of all (a tile that loses in two passes may win in one)
   for (int c = 0; c < (int)p->cands.size() && rc == PHI_OK; ++c) {
     p->cur = c;
     if (upload_worklist(p, s) != hipSuccess) {
       rc = PHI_ERR_HIP;
       break;
     }
+    const bool one_fits = p->gprec != PHI_G_KB && fused_lds_bytes(p->W().max_pitch) > 0;
     for (int pb : {0, 4 * cus}) {
       p->persist = pb;
-      p->flags = pb ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT);
-      double ms = 0;
-      if (!time_stages(true, true, ms)) {
-        rc = PHI_ERR_HIP;
-        break;
+      p->flags = (pb ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT)) & ~PHI_FUSED_GH;
+      for (bool one : {false, true}) {
+        if (one && !one_fits) continue;
+        double ms = 0;
+        if (!(one ? time_stages(false, false, ms, true) : time_stages(true, true, ms))) {
+          rc = PHI_ERR_HIP;
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          best_c = c;
+          best_p = pb;
+          best_one = one;
+        }
       }
-      if (ms < best) {
-        best = ms;
-        best_c = c;
-        best_p = pb;
-      }
+      if (rc != PHI_OK) break;
     }
   }
   p->cur = best_c;
   p->persist = best_p ? best_p : saved_persist;
   p->flags = best_p ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT);
+  p->flags = best_one ? (p->flags | PHI_FUSED_GH) : (p->flags & ~PHI_FUSED_GH);
   if (rc == PHI_OK && upload_worklist(p, s) != hipSuccess) rc = PHI_ERR_HIP;
-  // 2) with that tile and shape: the dual step in one pass over G, or two
-  p->flags &= ~PHI_FUSED_GH;
-  if (rc == PHI_OK && p->gprec != PHI_G_KB && fused_lds_bytes(p->W().max_pitch) > 0) {
-    double ms_two = 0, ms_one = 0;
-    if (!time_stages(true, true, ms_two) || !time_stages(false, false, ms_one, true)) {
-      rc = PHI_ERR_HIP;
-    } else if (ms_one < ms_two) {
-      p->flags |= PHI_FUSED_GH;
-    }
-  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return rc;

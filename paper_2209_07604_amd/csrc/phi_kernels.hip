@@ -1885,15 +1885,14 @@ __global__ __launch_bounds__(64) void k_build_g(BuildArgs a, int it0) {
 }
 
 // v+ = sigma_b scale_b c over each block's visibilities (fused dual step; a
-// block is one plan-order range): kVscaleChunks work-groups per block stream it
-constexpr int kVscaleChunks = 64;
+// block is one plan-order range): gridDim.x work-groups per block stream it
 __global__ __launch_bounds__(256) void k_vscale(const BlockInfo* __restrict__ blocks, float2* __restrict__ vis,
                                                 const double* __restrict__ sigma, const double* __restrict__ scale,
                                                 int b0) {
   const int b = b0 + blockIdx.y;
   const BlockInfo bi = blocks[b];
   const float f = (float)((sigma ? sigma[b] : 1.0) * scale[b]);
-  for (int64_t v = bi.v0 + (int64_t)blockIdx.x * 256 + threadIdx.x; v < bi.v1; v += (int64_t)kVscaleChunks * 256) {
+  for (int64_t v = bi.v0 + (int64_t)blockIdx.x * 256 + threadIdx.x; v < bi.v1; v += (int64_t)gridDim.x * 256) {
     const float2 c = vis[v];
     vis[v] = make_float2(f * c.x, f * c.y);
   }
@@ -2264,7 +2263,8 @@ hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s) {
 hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sigma, const double* scale, int b0,
                          int nb, hipStream_t s) {
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_vscale, dim3(kVscaleChunks, nb), dim3(256), 0, s, blocks, vis, sigma, scale, b0);
+  const int chunks = std::max(64, (4096 + nb - 1) / nb);  // >= 4096 work-groups over the chip
+  hipLaunchKernelGGL(k_vscale, dim3(chunks, nb), dim3(256), 0, s, blocks, vis, sigma, scale, b0);
   return hipGetLastError();
 }
 
