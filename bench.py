@@ -2,25 +2,42 @@
 
 One step = one l2ball_dual_step over every (channel, block) of the workload:
 Z + 2-D FFT, G gather with the residual, FP64 block norms and projection
-scale, G^H scatter of the new dual variable, merge, inverse FFT and Z^T.
+scale, G^H of the new dual variable, merge, inverse FFT and Z^T.
 
-Workload (default): 16 channels x 4 blocks, 1024 x 1024 image (2048 x 2048
-grid), 1.5M visibilities per channel, w-projection stencils 7x7 .. 17x17,
-30 dB input SNR, synthetic (seeded) data shaped like the paper's wideband VLA
-data.  Forms timed on the same data: plain FP32 (complex64 G, every stage
-launched per channel), batched FP32, batched FP16-G (the headline), batched
-BF16-G; batched forms replay a hipGraph.  On direction-independent workloads
-(one window size) the form batched_kb evaluates the Kaiser-Bessel taps in the
-kernels instead of reading stored G; fused_<prec> runs the dual step in one
-pass over G (PHI_FUSED_GH).  The autotuner picks one pass or two for the
-batched forms; twopass_<prec> times the same tuning with gather and scatter as
-separate passes, reported as roofline_two_pass.
+Workload (default C5): 16 channels x 1 block, 4096 x 4096 image (8192 x 8192
+grid), 8M visibilities per channel (1.28e8 in all), 7 x 7 Kaiser-Bessel rows
+(direction-independent data, the dimensionality-reduction experiment's
+shape), 30 dB input SNR, synthetic (seeded) data shaped like the paper's
+wideband VLA data.  G is computed on the device by the library's builder from
+the per-visibility grid coordinates (host windows with --host-g).
+
+Forms timed on the same resident data: plain FP32 (complex64 G, every stage
+launched per channel, two passes over G), batched FP32, batched FP16-G (the
+headline), the same FP16 plan with two passes over G, batched BF16-G.  The
+batched forms are autotuned (tile edge, launch shape, one pass or two over G)
+and replay a hipGraph.  Plans are built one precision at a time and freed
+after their forms, so the largest workloads fit the GPU.
+
+Roofline accounting: every stage is charged the algorithmic bytes of the
+minimal-pass design (per visibility 2 S^2 b_G + 48 B over the step, with G
+read by the gather and again by G^H; per channel 48 K + 8 N B), split over
+the stages that do that work; the one-pass stage, which replaces the gather
+and the G^H pass, is charged both G reads.  `roofline` is the dominant stage;
+`traffic` is the HBM byte count from a committed rocprofv3 counter run of the
+same kernels (null when the sources changed since).
+
+The CPU baseline is the FP64 oracle's dual step on whole channels of the same
+workload, one channel per process (the oracle as written: numpy.fft and
+scipy.sparse, single-threaded in each process), timed together on the host.
+Its channel-0 inputs also run through every GPU form, which gives each form's
+error against FP64.
 
 Prints ONE JSON line.  Inputs are resident in HBM before timing starts.
 """
 import argparse
 import hashlib
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -32,6 +49,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Φ+Φ† visibilities/s and HBM GB/s, batched FP16-G vs plain FP32 at ≤2e-3 err"
 HBM_PEAK_GBS = 8000.0
+STAGES_G = ("gather", "scatter", "dual_gs")
 
 
 def log(*a):
@@ -45,9 +63,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel, launch_alg_bytes):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel sources; else None."""
+def traffic_for(workload, kernel):
+    """HBM bytes per step of one stage from the committed rocprofv3 counter
+    summary of this workload, if it was taken on the current kernel sources;
+    else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -55,15 +74,127 @@ def traffic_for(kernel, launch_alg_bytes):
         t = json.load(open(path))
     except ValueError:
         return None
-    if t.get("source_hash") != kernel_source_hash():
+    w = t.get("workloads", {}).get(workload)
+    if not w or w.get("source_hash") != kernel_source_hash():
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("bytes_per_launch")
+    k = w.get("stages", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_step")
 
 
-def generate(name, log_every=8, channels=0, windows=True):
-    """Problem, per-block (base, S, windows or None) and per-block continuous
-    grid coordinates [M, 2] (for the Kaiser-Bessel form)."""
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    mem_gb = avail_gb = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                mem_gb = int(line.split()[1]) / 1e6
+            elif line.startswith("MemAvailable:"):
+                avail_gb = int(line.split()[1]) / 1e6
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model, "ram_GB": mem_gb,
+            "ram_available_GB": avail_gb}
+
+
+# ------------------------------------------------------------ CPU baseline
+def _oracle_worker(config, l, sample, barrier, q_early, q_out, omp):
+    """One channel of the workload through the FP64 oracle (own process)."""
+    os.environ["OMP_NUM_THREADS"] = str(omp)
+    try:
+        import synth
+        import oracle
+        from oracle.dual import block_radii
+        prob = synth.make_problem(config)
+        sel = [(l, b) for b in range(prob.n_blocks[l])]
+        t0 = time.time()
+        op = oracle.Operator.from_problem(prob, None, blocks=sel)
+        x = prob.image(l).astype(np.float64)
+        Y0 = op.forward({l: x})
+        ml = float(sum(prob.n_vis[l]))
+        # 30 dB input SNR, then whitened: theta = 1 / sigma (in place on the CSR data)
+        theta = 1.0 / np.sqrt(sum(float(np.vdot(y, y).real) for y in Y0) / ml * 1e-3)
+        for blk in op.blocks:
+            blk.G.data *= theta
+            blk.theta = theta
+        rng = np.random.default_rng(np.random.SeedSequence((220907604, 777, l)))
+        Y = [theta * y + (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) / np.sqrt(2.0)
+             for y in Y0]
+        V = [0.1 * (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
+        eps = block_radii(prob.n_vis[l])
+        del Y0
+        if sample:
+            q_early.put({"l": l, "theta": theta, "Y": Y, "V": V, "eps": eps, "setup_s": time.time() - t0})
+        barrier.wait(timeout=1800)
+        t1 = time.perf_counter()
+        Vp, grad, rho, res = oracle.dual_step(op, {l: 0.5 * x}, V, Y, eps)
+        dt = time.perf_counter() - t1
+        out = {"l": l, "M": int(ml), "s": dt}
+        if sample:
+            out.update(Vp=np.concatenate(Vp), grad=grad[l], rho=rho, res=res)
+        q_out.put(out)
+    except BaseException as e:  # report, never hang the parent
+        q_out.put({"l": l, "error": repr(e)})
+        if sample:
+            q_early.put({"l": l, "error": repr(e)})
+        try:
+            barrier.abort()
+        except Exception:
+            pass
+
+
+class CpuBaseline:
+    """The oracle on `workers` whole channels, one per spawned process
+    (started before the GPU is touched).  Channel 0 is the error sample."""
+
+    def __init__(self, config, L, workers):
+        ctx = mp.get_context("spawn")
+        self.chans = sorted(set(np.linspace(0, L - 1, workers).round().astype(int).tolist()))
+        n = len(self.chans)
+        hi = host_info()
+        omp = max(1, (hi["usable_cpus"] or 1) // n)
+        self.barrier = ctx.Barrier(n)
+        self.q_early, self.q_out = ctx.Queue(), ctx.Queue()
+        self.procs = [ctx.Process(target=_oracle_worker,
+                                  args=(config, l, l == self.chans[0], self.barrier, self.q_early, self.q_out, omp),
+                                  daemon=True) for l in self.chans]
+        for p in self.procs:
+            p.start()
+        self._sample = None
+        self.host = hi
+
+    def sample(self):
+        """Channel-0 inputs of the oracle (blocks until they are ready)."""
+        if self._sample is None:
+            s = self.q_early.get(timeout=1800)
+            if "error" in s:
+                raise RuntimeError("oracle worker failed: " + s["error"])
+            self._sample = s
+        return self._sample
+
+    def results(self):
+        outs = [self.q_out.get(timeout=1800) for _ in self.procs]
+        for p in self.procs:
+            p.join(timeout=60)
+        bad = [o for o in outs if "error" in o]
+        if bad:
+            raise RuntimeError("oracle worker failed: %s" % bad[0]["error"])
+        return outs
+
+
+# --------------------------------------------------------------- workload
+def generate(name, channels=0, host_windows=False):
+    """Problem and per-block (base, S, windows or None, kappa [M, 2], w-table)."""
     import synth
     prob = synth.make_problem(name)
     if channels and channels < prob.L:
@@ -72,78 +203,32 @@ def generate(name, log_every=8, channels=0, windows=True):
                                   n_vis=[prob.n_vis[l] for l in sel],
                                   nu=None if prob.nu is None else prob.nu[sel])
     t0 = time.time()
-    blocks, kappas, wtab = [], [], []
+    blocks = []
     K = np.array([prob.Ky, prob.Kx], dtype=np.float64)
+    nb = len(prob.block_list())
     for k, (l, b) in enumerate(prob.block_list()):
         blk = prob.block(l, b)
-        w = blk.windows(np.complex64)[0] if windows else None
-        blocks.append((blk.base, blk.S, w))
-        kappas.append(blk.omega * K / (2 * np.pi))
-        # the generator's w-kernel tables (half-width h, chirp parameter a)
-        # for rows without DDE, as the device G builder takes them
-        if not prob.dde:
-            h = ((blk._skw - 7) // 2).astype(np.int32)
-            a = prob.w_max_cells * blk.w
-            wtab.append((h, np.where(np.round(a) > h, h.astype(np.float64), a)))
-        if k % log_every == 0:
-            log("[bench] generated block %d/%d (%.0f s)" % (k + 1, len(prob.block_list()), time.time() - t0))
+        w = blk.windows(np.complex64)[0] if host_windows else None
+        blocks.append(dict(base=blk.base, S=blk.S, windows=w, kappa=blk.omega * K / (2 * np.pi),
+                           h=blk.w_h, a=blk.w_a))
+        if k % 8 == 0 or k == nb - 1:
+            log("[bench] generated block %d/%d (%.0f s)" % (k + 1, nb, time.time() - t0))
     generate.seconds = time.time() - t0
-    return prob, blocks, kappas, wtab
+    return prob, blocks
 
 
-def cpu_baseline(prob, plan, theta, budget_s=30.0):
-    """The FP64 oracle's dual step on channel 0 of the same workload, timed on
-    the host cores (numpy/scipy as they stand).  The same inputs then go
-    through the headline GPU plan, and its channel-0 outputs are compared with
-    the oracle's (error of the timed form against FP64)."""
-    import torch
-    import oracle
-    from oracle.dual import block_radii
-    t_setup = time.time()
-    nb0 = prob.n_blocks[0]
-    sel = [(0, b) for b in range(nb0)]
-    rng = np.random.default_rng(5)
-    op = oracle.Operator.from_problem(prob, {k: theta[i] for i, k in enumerate(sel)}, blocks=sel)
-    x = prob.image(0).astype(np.float64)
-    Y = op.forward({0: x})
-    V = [0.1 * (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) for y in Y]
-    Y = [y + (rng.standard_normal(len(y)) + 1j * rng.standard_normal(len(y))) / np.sqrt(2) for y in Y]
-    eps = block_radii(prob.n_vis[0])
-    log("[bench] cpu baseline set-up %.1f s" % (time.time() - t_setup))
-    n, t_tot = 0, 0.0
-    while n == 0 or (t_tot < budget_s / 3 and n < 3):
-        t0 = time.perf_counter()
-        Vp_o, grad_o, rho_o, res_o = oracle.dual_step(op, {0: 0.5 * x}, V, Y, eps)
-        t_tot += time.perf_counter() - t0
-        n += 1
-    m = int(sum(prob.n_vis[0]))
-    base = {"value": m * n / t_tot, "unit": "visibilities/s", "cores": 1, "kind": "oracle",
-            "sample": "channel 0 (%d blocks, %d visibilities, %dx%d grid) of the same workload, FP64 "
-                      "numpy/scipy dual step, %d run(s), %.2f s each; numpy.fft and scipy.sparse run "
-                      "single-threaded" % (nb0, m, prob.Ky, prob.Kx, n, t_tot / n)}
-    # the same channel-0 inputs through the GPU plan (other channels: zero data)
-    M = plan.M
-    vh = np.zeros(M, np.complex64)
-    yh = np.zeros(M, np.complex64)
-    vh[:m] = np.concatenate(V)
-    yh[:m] = np.concatenate(Y)
-    dev = plan.device
-    xt = torch.zeros((plan.L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
-    xt[0] = torch.from_numpy((0.5 * x).astype(np.float32))
-    v = plan.to_plan(torch.from_numpy(vh).to(dev))
-    y = plan.to_plan(torch.from_numpy(yh).to(dev))
-    e_all = np.ones(plan.nblk)
-    e_all[:nb0] = eps
-    grad, rho, res = plan.dual_step(xt, v, y, torch.from_numpy(e_all).to(dev))
-    vp = plan.from_plan(v).cpu().numpy()[:m].astype(np.complex128)
-    g0 = grad[0].cpu().numpy().astype(np.float64)
-    r0 = rho.cpu().numpy()[:nb0]
-
-    def rel(a, b):
-        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    err = {"v_plus": rel(vp, np.concatenate(Vp_o)), "grad": rel(g0, grad_o[0]), "rho": rel(r0, rho_o),
-           "sample": "channel 0, all %d blocks, same inputs as the cpu baseline" % nb0}
-    return base, err
+def stage_alg_bytes(info, L, N, K):
+    """Algorithmic HBM bytes per step of every stage (minimal-pass design:
+    G read by the gather and again by G^H; v and y read, c written and read,
+    v+ written; x read, half grid written and read, grid written and read per
+    direction).  The one-pass stage is charged the gather's and the G^H
+    pass's bytes except the c read and v+ write, which the v+ scale does."""
+    T, M = float(info["n_taps"]), float(info["n_vis_total"])
+    G = float(info["g_bytes"])
+    return {"rowfft_fwd": L * (4.0 * N + 4.0 * K), "colfft_fwd": L * 12.0 * K,
+            "gather": G + 28.0 * M + L * 8.0 * K, "scatter": G + 20.0 * M,
+            "dual_gs": 2.0 * G + 32.0 * M + L * 8.0 * K, "vscale": 16.0 * M, "finalize": 0.0,
+            "merge": L * 8.0 * K, "colfft_inv": L * 12.0 * K, "rowfft_inv": L * (4.0 * K + 4.0 * N)}
 
 
 def _event_ms(fn, n):
@@ -158,19 +243,22 @@ def _event_ms(fn, n):
     return e0.elapsed_time(e1) / n
 
 
-def stream_copy_gbs(dev, mib=2048):
-    """Device-to-device copy rate (read + write bytes / time) of a plain
-    library copy of a 2 GiB buffer: a practical streaming bound on this GPU."""
+def stream_rates(dev, mib=2048):
+    """A plain library device copy (read + write bytes / time) and a plain
+    library reduction (read bytes / time) of 2 GiB: practical streaming
+    rates of this GPU beside the 8 TB/s specification."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.ones(n, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     for _ in range(3):
         dst.copy_(src)
+        src.sum()
     torch.cuda.synchronize()
-    ms = _event_ms(lambda: dst.copy_(src), 10)
+    copy_ms = _event_ms(lambda: dst.copy_(src), 10)
+    sum_ms = _event_ms(lambda: src.sum(), 10)
     del src, dst
-    return 2.0 * n * 4 / (ms * 1e-3) / 1e9
+    return {"copy_GBs": 2.0 * n * 4 / (copy_ms * 1e-3) / 1e9, "read_GBs": n * 4 / (sum_ms * 1e-3) / 1e9}
 
 
 def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
@@ -213,6 +301,7 @@ def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
     stages, calls = p.get_timing()
     px = L * p.ny * p.nx
     prim_ms = stages["pdfb_primal"] / max(calls, 1)
+    del xi, xti, v, e, grad, var, state, w, img, yv
     out["pdfb"] = {"ms_per_iter": ms, "primal_ms": prim_ms, "eps_update_ms": stages["eps_update"] / max(calls, 1),
                    "primal_alg_bytes": 16.0 * px,
                    "primal_GBs": 16.0 * px / (prim_ms * 1e-3) / 1e9,
@@ -221,92 +310,42 @@ def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
     return out
 
 
-def time_gbuild(p, kappas, wtab, xt, v0, y, eps, dev):
-    """Rebuild every block's G on the device (phi_plan_build_g) from the
-    generator's tables, timed on the wall clock (each call is synchronous),
-    then one dual step on the rebuilt G against the step on the host-loaded
-    G (same inputs)."""
+def run_sample(p, prob, smp, theta, flags, dev):
+    """The oracle's channel-0 inputs through plan p (other channels zero):
+    (v+ channel 0 user order, grad channel 0, rho, res of channel 0's blocks)."""
     import torch
-    v = v0.clone()
-    grad0, _, _ = p.dual_step(xt, v, y, eps)
-    vp0, grad0 = v.clone(), grad0.clone()
-    tabs = [(torch.from_numpy(np.ascontiguousarray(k)).to(dev), torch.from_numpy(h).to(dev),
-             torch.from_numpy(np.ascontiguousarray(a)).to(dev)) for k, (h, a) in zip(kappas, wtab)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for b, (k, h, a) in enumerate(tabs):
-        p.build_g(b, k, h, a, J=7)
-    ms = (time.perf_counter() - t0) * 1e3
-    v = v0.clone()
-    grad1, _, _ = p.dual_step(xt, v, y, eps)
-    torch.cuda.synchronize()
-    rel = lambda a_, b_: float(torch.linalg.vector_norm((a_ - b_).to(torch.complex128)) /
-                               torch.linalg.vector_norm(b_.to(torch.complex128)))
-    info = p.info()
-    return {"ms": ms, "taps": int(info["n_taps"]), "G_bytes": int(info["g_bytes"]),
-            "G_GB_per_s_written": info["g_bytes"] / (ms * 1e-3) / 1e9,
-            "host_generation_s": generate.seconds,
-            "dual_step_rel_diff_vs_host_G": {"v_plus": rel(v, vp0), "grad": rel(grad1, grad0)},
-            "note": "FP64 rows (Kaiser-Bessel taps (*) w-chirp) rounded once to the stored precision; wall "
-                    "clock of one synchronous call per block; host_generation_s is the seeded generator "
-                    "building the same windows on the host; the host-loaded G came from complex64 windows "
-                    "(rounded twice), hence the small step difference"}
-
-
-def run_dr(args, prob, blocks, theta, y_user, starts, s_y, s_x, results, dev):
-    """Reduce every block (host, FP64) and time the reduced dual step with the
-    same precision and launch form as the headline; returns a summary."""
-    import torch
-    from paper_2209_07604_amd import Plan, dr_reduce, GRAPH, PERSISTENT
-    t0 = time.time()
-    outs = []
-    for k, (b_, S_, w_) in enumerate(blocks):
-        outs.append(dr_reduce(prob.Ky, prob.Kx, b_, S_, w_, theta[k],
-                              y_user[starts[k]:starts[k + 1]].astype(np.complex128)))
-    t_red = time.time() - t0
-    n_red = [len(o["S"]) for o in outs]
-    log("[bench] reduction %.1f s, M' per block %s" % (t_red, n_red))
-    prec = "f16"
-    p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_red, np.concatenate([o["base"] for o in outs]),
-             np.concatenate([o["S"] for o in outs]), s_y, s_x, None, g_prec=prec, device=dev)
-    for k, o in enumerate(outs):
-        p.load_g(k, o["windows"].astype(np.complex64))
-    yr = p.to_plan(torch.from_numpy(np.concatenate([o["y"] for o in outs]).astype(np.complex64)).to(dev))
-    del outs
-    p.autotune(3)
-    p.set_flags(GRAPH | (PERSISTENT if p.info()["persist_blocks"] else 0))
-    mr = int(sum(n_red))
-    eps = torch.tensor([np.sqrt(m + 2.0 * np.sqrt(m)) for m in n_red], dtype=torch.float64, device=dev)
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(7)
-    v = (0.1 * torch.complex(torch.randn(mr, generator=gen, device=dev),
-                             torch.randn(mr, generator=gen, device=dev))).contiguous()
-    xt = torch.from_numpy(np.stack([0.5 * prob.image(l) for l in range(prob.L)])).to(dev)
-    grad = torch.empty_like(xt)
-    rho = torch.empty(len(n_red), dtype=torch.float64, device=dev)
-    res = torch.empty_like(rho)
-    for _ in range(args.warmup):
-        p.dual_step(xt, v, yr, eps, None, grad, rho, res)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        p.dual_step(xt, v, yr, eps, None, grad, rho, res)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    info = p.info()
-    M = int(sum(len(s) for (_, s, _) in blocks))
-    ref = results.get("batched_f16")
-    out = {"M": M, "M_reduced": mr, "M_over_M_reduced": M / mr, "taps_G": ref["info"]["n_taps"] if ref else None,
-           "taps_H": info["n_taps"], "g_bytes_f16": ref["info"]["g_bytes"] if ref else None,
-           "h_bytes_f16": info["g_bytes"], "reduce_host_s": t_red, "ms_per_step_reduced": ms,
-           "ms_per_step_unreduced": ref["ms_per_step"] if ref else None,
-           "visibilities_per_s_reduced": M / (ms * 1e-3), "tile": info["tile"]}
-    if ref:
-        out["speedup"] = ref["ms_per_step"] / ms
-    log("[bench] reduced step: %s" % out)
+    nb0 = prob.n_blocks[0]
+    m0 = int(sum(prob.n_vis[0]))
+    th = np.array(theta, dtype=np.float64)
+    th[:nb0] = smp["theta"]
+    p.set_theta(th)
+    vh = np.zeros(p.M, np.complex64)
+    yh = np.zeros(p.M, np.complex64)
+    vh[:m0] = np.concatenate(smp["V"])
+    yh[:m0] = np.concatenate(smp["Y"])
+    xt = torch.zeros((p.L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
+    xt[0] = torch.from_numpy((0.5 * prob.image(0)).astype(np.float32))
+    v = p.to_plan(torch.from_numpy(vh).to(dev))
+    y = p.to_plan(torch.from_numpy(yh).to(dev))
+    e_all = np.ones(p.nblk)
+    e_all[:nb0] = smp["eps"]
+    p.set_flags(flags)
+    grad, rho, res = p.dual_step(xt, v, y, torch.from_numpy(e_all).to(dev))
+    p.check()
+    out = (p.from_plan(v)[:m0].cpu().numpy(), grad[0].cpu().numpy(), rho[:nb0].cpu().numpy(),
+           res[:nb0].cpu().numpy())
+    p.set_theta(theta)
+    del v, y, xt, grad, rho, res
     return out
+
+
+def rel_err(gpu, ref):
+    def rel(a, b):
+        a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(a) else np.float64)
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    vp, g, rho, res = gpu
+    return {"v_plus": rel(vp, ref["Vp"]), "grad": rel(g, ref["grad"]), "rho": rel(rho, ref["rho"]),
+            "res": rel(res, ref["res"])}
 
 
 def main():
@@ -314,18 +353,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--config", default="C2")
-    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_f16,twopass_f16,batched_bf16")
+    ap.add_argument("--config", default="C5")
+    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_bf16,twopass_f16,batched_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=4,
+                    help="channels of the CPU baseline, one process each (capped by host memory and cores)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile edge (skips the autotuner)")
     ap.add_argument("--persist", type=int, default=0, help="persistent G-stage grid with --tile")
     ap.add_argument("--channels", type=int, default=0, help="use this many channels of the configuration")
-    ap.add_argument("--dr", action="store_true",
-                    help="also time the visibility-gridding reduced step (Section 3.4) on the same data")
-    ap.add_argument("--no-gbuild", action="store_true", help="skip timing the device G builder")
-    ap.add_argument("--device-g", action="store_true",
-                    help="build G on the device from the generator's tables (no host windows)")
+    ap.add_argument("--host-g", action="store_true",
+                    help="load G from host windows built by the generator instead of the device builder")
+    ap.add_argument("--no-extras", action="store_true", help="skip forward/adjoint/PDFB timings")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -333,74 +372,54 @@ def main():
         print("bench.py measures one GPU: the data-fidelity step shards by channel with no exchange, "
               "and this build runs on a single MI355X; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
+    import synth
+    forms = [f for f in args.forms.split(",") if f]
+    cfg_prob = synth.make_problem(args.config)
+    device_g = not args.host_g and not cfg_prob.dde
+    if not device_g and not args.host_g:
+        log("[bench] %s has DDE rows: G from host windows" % args.config)
+    # the CPU baseline's processes start before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        hi = host_info()
+        per_chan_gb = 2.5 * 16.0 * cfg_prob.M_total / cfg_prob.L * 49 / 1e9 + 4.0
+        cap_mem = int(max(1.0, ((hi["ram_available_GB"] or 64.0) * 0.6) // per_chan_gb))
+        nw = max(1, min(args.cpu_workers, cfg_prob.L, hi["usable_cpus"] or 1, cap_mem))
+        cpu = CpuBaseline(args.config, cfg_prob.L, nw)
+        log("[bench] cpu baseline: %d oracle process(es) on channels %s, host %s" % (nw, cpu.chans, cpu.host))
 
     import torch
     from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
-    forms = [f for f in args.forms.split(",") if f]
-    if args.device_g and args.dr:
-        print("--device-g and --dr are exclusive (the reduction needs host windows)", file=sys.stderr)
-        sys.exit(2)
-    prob, blocks, kappas, wtab = generate(args.config, channels=args.channels,
-                                          windows=not args.device_g and
-                                          (args.dr or any(not f.endswith("_kb") for f in forms)))
-    if args.device_g and not wtab:
-        print("--device-g needs a workload without DDE", file=sys.stderr)
-        sys.exit(2)
+    prob, blocks = generate(args.config, channels=args.channels, host_windows=not device_g)
     L = prob.L
-    n_vis = [len(s) for (_, s, _) in blocks]
-    base = np.concatenate([b for (b, _, _) in blocks])
-    S = np.concatenate([s for (_, s, _) in blocks])
+    t0 = time.time()
+    n_vis = [len(b["S"]) for b in blocks]
+    base = np.concatenate([b["base"] for b in blocks])
+    S = np.concatenate([b["S"] for b in blocks])
     s_y, s_x = prob.deapodisation()
     M = int(len(S))
-    precs = sorted({f.split("_")[1] for f in forms}, key=["c64", "f16", "bf16", "kb"].index)
-    plans = {}
-    t0 = time.time()
-    for prec in precs:
-        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
-        for k, (_, _, w) in enumerate(blocks):
-            if prec == "kb":
-                p.load_kb(k, kappas[k])   # taps evaluated in the kernels
-            elif args.device_g:           # rows computed on the device from the generator's tables
-                p.build_g(k, torch.from_numpy(np.ascontiguousarray(kappas[k])).to(dev),
-                          torch.from_numpy(wtab[k][0]).to(dev),
-                          torch.from_numpy(np.ascontiguousarray(wtab[k][1])).to(dev), J=7)
-            else:
-                p.load_g(k, w)
-        plans[prec] = p
-        log("[bench] plan %s ready (%.0f s), info %s" % (prec, time.time() - t0, p.info()))
-    if not args.dr:
-        del blocks
+    Kc, Nc = prob.Ky * prob.Kx, prob.Ny * prob.Nx
+    precs = []
+    for f in forms:
+        pr = f.split("_")[1]
+        if pr not in precs:
+            precs.append(pr)
+    head = "batched_f16" if "batched_f16" in forms else forms[-1]
+    hprec = head.split("_")[1]
+    precs = [q for q in precs if q != hprec] + [hprec]   # the headline plan is built last and kept
 
-    # inputs: x~ = x/2, y = theta Phi0 x + n at 30 dB (theta from the c64 form), v ~ 0.1 CN
+    x = torch.from_numpy(np.stack([prob.image(l) for l in range(L)])).to(dev)
+    xt = (0.5 * x).contiguous()
+    log("[bench] images resident (%.0f s)" % (time.time() - t0))
     gen = torch.Generator(device=dev)
     gen.manual_seed(220907604)
-    x = torch.from_numpy(np.stack([prob.image(l) for l in range(L)])).to(dev)
-    log("[bench] images ready (%.0f s)" % (time.time() - t0))
-    pref = plans[precs[0]]
-    y0 = pref.forward(x)
-    ch_of_blk = np.repeat(np.arange(L), prob.n_blocks)
-    starts = np.concatenate([[0], np.cumsum(n_vis)])
-    pw = np.zeros(L)
-    y0h = y0.abs().square().double()
-    for k in range(len(n_vis)):
-        pw[ch_of_blk[k]] += y0h[starts[k]:starts[k + 1]].sum().item()
-    m_ch = np.array([sum(m) for m in prob.n_vis], dtype=np.float64)
-    theta_ch = 1.0 / np.sqrt(pw / m_ch * 1e-3)
-    log("[bench] noiseless data and channel powers ready (%.0f s)" % (time.time() - t0))
-    theta = theta_ch[ch_of_blk]
-    noise = torch.complex(torch.randn(M, generator=gen, device=dev), torch.randn(M, generator=gen, device=dev))
-    noise = noise * (0.5 ** 0.5)
-    th_vis = torch.from_numpy(np.repeat(theta, n_vis).astype(np.float32)).to(dev)
-    y_plan = {}
-    for prec, p in plans.items():
-        p.set_theta(theta)
-        y_plan[prec] = p.to_plan((th_vis * pref.from_plan(y0) + noise).contiguous())
+    noise = None
+    y_user = theta = None
     v_init = (0.1 * torch.complex(torch.randn(M, generator=gen, device=dev),
                                   torch.randn(M, generator=gen, device=dev))).contiguous()
-    xt = (0.5 * x).contiguous()
     # chi-square radii (eq. 2): eps_l^2 = M_l + 2 sqrt(M_l), eps_lb^2 = eps_l^2 M_lb / M_l
     eps_h = []
     for nv in prob.n_vis:
@@ -408,78 +427,133 @@ def main():
         eps_h += [np.sqrt((ml + 2.0 * np.sqrt(ml)) * m / ml) for m in nv]
     eps = torch.tensor(eps_h, dtype=torch.float64, device=dev)
     nblk = len(n_vis)
-    torch.cuda.synchronize()
-    log("[bench] inputs resident (%.0f s)" % (time.time() - t0))
+    ch_of_blk = np.repeat(np.arange(L), prob.n_blocks)
+    starts = np.concatenate([[0], np.cumsum(n_vis)])
 
-    results = {}
-    for form in forms:
-        kind, prec = form.split("_")
-        p = plans[prec]
-        v = p.to_plan(v_init)
-        v0 = v.clone()
-        grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
-        rho = torch.empty(nblk, dtype=torch.float64, device=dev)
-        res = torch.empty(nblk, dtype=torch.float64, device=dev)
-        if kind in ("batched", "fused", "twopass") and args.tile:
-            p.set_tuning(args.tile, args.persist)
-        elif kind in ("batched", "fused") and not args.no_autotune:
-            rc = p.autotune(3)
-            log("[bench] autotune %s -> rc %d, tile %d, persist %d" % (
-                prec, rc, p.info()["tile"], p.info()["persist_blocks"]))
-        # the autotuner may have chosen the one-pass dual step (info "fused");
-        # fused_<prec> forces it; plain_<prec> and twopass_<prec> (the batched
-        # form on the same tuning, gather and scatter as separate passes) never
-        # use it
-        fused = kind == "fused" or (kind == "batched" and bool(p.info()["fused"]))
-        flags_now = (p.info()["persist_blocks"] and PERSISTENT) | (FUSED_GH if fused else 0)
-        p.set_flags((PER_CHANNEL if kind == "plain" else GRAPH) | flags_now)
-        log("[bench] %s: warm-up" % form)
-        for _ in range(args.warmup):
+    results, samples, gb_build = {}, {}, {}
+    hp = None
+    for prec in precs:
+        tp = time.time()
+        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
+        tile0 = p.info()["tile"]
+        log("[bench] plan %s created (%.1f s), workspace %.1f GB" % (prec, time.time() - tp, p.workspace_size() / 1e9))
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for k, b in enumerate(blocks):
+            if device_g:   # rows computed on the device from the generator's tables
+                p.build_g(k, torch.from_numpy(np.ascontiguousarray(b["kappa"])).to(dev),
+                          torch.from_numpy(np.ascontiguousarray(b["h"])).to(dev),
+                          torch.from_numpy(np.ascontiguousarray(b["a"])).to(dev), J=7)
+            else:
+                p.load_g(k, b["windows"])
+        torch.cuda.synchronize()
+        gb_build[prec] = time.perf_counter() - tb
+        info0 = p.info()
+        log("[bench] plan %s G ready (%.1f s), info %s" % (prec, gb_build[prec], info0))
+        if y_user is None:
+            # y = theta Phi0 x + n at 30 dB per channel (theta from this plan's noiseless forward)
+            y0 = p.from_plan(p.forward(x))
+            pw = np.zeros(L)
+            y0h = y0.abs().square().double()
+            for k in range(nblk):
+                pw[ch_of_blk[k]] += y0h[starts[k]:starts[k + 1]].sum().item()
+            del y0h
+            m_ch = np.array([sum(m) for m in prob.n_vis], dtype=np.float64)
+            theta = (1.0 / np.sqrt(pw / m_ch * 1e-3))[ch_of_blk]
+            noise = torch.complex(torch.randn(M, generator=gen, device=dev), torch.randn(M, generator=gen, device=dev))
+            th_vis = torch.from_numpy(np.repeat(theta, n_vis).astype(np.float32)).to(dev)
+            y_user = (th_vis * y0 + noise * (0.5 ** 0.5)).contiguous()
+            del y0, noise, th_vis
+        p.set_theta(theta)
+        y = p.to_plan(y_user)
+        order = ["plain", "batched", "fused", "twopass"]
+        for form in sorted([f for f in forms if f.split("_")[1] == prec], key=lambda f: order.index(f.split("_")[0])):
+            kind = form.split("_")[0]
+            v = p.to_plan(v_init)
+            v0 = v.clone()
+            grad = torch.empty((L, prob.Ny, prob.Nx), dtype=torch.float32, device=dev)
+            rho = torch.empty(nblk, dtype=torch.float64, device=dev)
+            res = torch.empty(nblk, dtype=torch.float64, device=dev)
+            if kind in ("batched", "fused", "twopass") and args.tile:
+                p.set_tuning(args.tile, args.persist)
+            elif kind in ("batched", "fused") and not args.no_autotune:
+                ta = time.time()
+                p.autotune(3)
+                log("[bench] autotune %s (%.1f s) -> tile %d, persist %d, one pass %d" % (
+                    prec, time.time() - ta, p.info()["tile"], p.info()["persist_blocks"], p.info()["fused"]))
+            # batched_<prec> keeps the autotuner's choice of one pass or two;
+            # fused_<prec> forces one pass; plain_ and twopass_ use two passes
+            # (twopass_ on the batched form's tuning)
+            fused = kind == "fused" or (kind == "batched" and bool(p.info()["fused"]))
+            flags_now = (PERSISTENT if (kind != "plain" and p.info()["persist_blocks"]) else 0) | \
+                (FUSED_GH if fused else 0)
+            if kind == "plain":
+                p.set_tuning(tile0, 0)
+            graph_flags = (PER_CHANNEL if kind == "plain" else GRAPH) | flags_now
+            p.set_flags(graph_flags)
+            log("[bench] %s: warm-up" % form)
+            for _ in range(args.warmup):
+                v.copy_(v0)
+                p.dual_step(xt, v, y, eps, None, grad, rho, res)
             v.copy_(v0)
-            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
-        v.copy_(v0)
-        torch.cuda.synchronize()
-        log("[bench] %s: timing %d steps" % (form, args.steps))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t_wall = time.perf_counter()
-        e0.record()
-        for _ in range(args.steps):
-            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t_wall
-        ms = e0.elapsed_time(e1) / args.steps
-        p.check()
-        # per-stage HIP-event timing over a second run of the same steps
-        # (stage-by-stage launches of the same kernels on the same stream)
-        p.set_flags((PER_CHANNEL if kind == "plain" else 0) | flags_now)
-        v.copy_(v0)
-        torch.cuda.synchronize()
-        p.set_timing(True)
-        for _ in range(args.steps):
-            p.dual_step(xt, v, y_plan[prec], eps, None, grad, rho, res)
-        torch.cuda.synchronize()
-        p.set_timing(False)
-        stages, calls = p.get_timing()
-        info = info_t = p.info()
-        results[form] = dict(ms_per_step=ms, tile=info_t["tile"], persist_blocks=info_t["persist_blocks"],
-                             one_pass=bool(fused), wall_ms_per_step=1e3 * wall / args.steps,
-                             vis_per_s=M / (ms * 1e-3),
-                             alg_GBs=info["alg_bytes_dual_step"] / (ms * 1e-3) / 1e9,
-                             stage_ms={k_: v_ / max(calls, 1) for k_, v_ in stages.items()},
-                             info=info, rho0=float(rho[0].item()))
-        log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
-            form, ms, M / (ms * 1e-3), {k_: round(v_ / max(calls, 1), 3) for k_, v_ in stages.items()}))
+            torch.cuda.synchronize()
+            log("[bench] %s: timing %d steps" % (form, args.steps))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t_wall = time.perf_counter()
+            e0.record()
+            for _ in range(args.steps):
+                p.dual_step(xt, v, y, eps, None, grad, rho, res)
+            e1.record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t_wall
+            ms = e0.elapsed_time(e1) / args.steps
+            p.check()
+            # per-stage HIP-event timing over a second run of the same steps
+            # (stage-by-stage launches of the same kernels on the same stream)
+            p.set_flags((PER_CHANNEL if kind == "plain" else 0) | flags_now)
+            v.copy_(v0)
+            torch.cuda.synchronize()
+            p.set_timing(True)
+            for _ in range(args.steps):
+                p.dual_step(xt, v, y, eps, None, grad, rho, res)
+            torch.cuda.synchronize()
+            p.set_timing(False)
+            stages, calls = p.get_timing()
+            info = p.info()
+            st_ms = {k_: v_ / max(calls, 1) for k_, v_ in stages.items() if v_ > 0}
+            alg = stage_alg_bytes(info, L, Nc, Kc)
+            b_step = sum(alg[k_] for k_ in st_ms if k_ in alg and not (fused and k_ in ("gather", "scatter")))
+            results[form] = dict(ms_per_step=ms, tile=info["tile"], persist_blocks=info["persist_blocks"],
+                                 one_pass=bool(fused), wall_ms_per_step=1e3 * wall / args.steps,
+                                 vis_per_s=M / (ms * 1e-3), stage_ms=st_ms,
+                                 alg_bytes_step=b_step, alg_GBs=b_step / (ms * 1e-3) / 1e9,
+                                 hbm_frac=b_step / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 g_bytes=int(info["g_bytes"]), partial_bytes=int(info["partial_bytes"]),
+                                 pitch_classes=int(info["pitch_classes"]), info=info, graph_flags=graph_flags)
+            log("[bench] %s: %.3f ms/step, %.3g vis/s, stages %s" % (
+                form, ms, M / (ms * 1e-3), {k_: round(v_, 3) for k_, v_ in st_ms.items()}))
+            del v, v0, grad, rho, res
+            if cpu is not None:
+                smp = cpu.sample()
+                samples[form] = run_sample(p, prob, smp, theta, graph_flags, dev)
+                log("[bench] %s: channel-0 oracle sample run" % form)
+        if prec == hprec:
+            hp = p
+            hp_y = y
+        else:
+            del y, p
+            torch.cuda.empty_cache()
 
-    line_gb = None
-    if wtab and not args.no_gbuild and "batched_f16" in results:
-        log("[bench] device G builder")
-        line_gb = time_gbuild(plans["f16"], kappas, wtab, xt, plans["f16"].to_plan(v_init), y_plan["f16"], eps, dev)
-        log("[bench] G builder: %s" % line_gb)
-    del kappas
-    if args.dr:
-        line_dr = run_dr(args, prob, blocks, theta, (th_vis * pref.from_plan(y0) + noise).cpu().numpy(),
-                         starts, s_y, s_x, results, dev)
+    r = results[head]
+    info = r["info"]
+    hflags = r["graph_flags"]
+    hp.set_flags(hflags)
+    line_extra = {}
+    if not args.no_extras:
+        log("[bench] %s: forward, adjoint and PDFB iterations" % head)
+        extras = time_extras(hp, x, xt, hp.to_plan(v_init), hp_y, eps, args.steps, args.warmup, dev)
+        line_extra = {"forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
+                      "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS)}
     if args.calib_copy_mib:
         n = args.calib_copy_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device=dev)
@@ -489,29 +563,23 @@ def main():
         torch.cuda.synchronize()
         log("[bench] calibration copy of %d MiB done" % args.calib_copy_mib)
         del src, dst
-    head = "batched_f16" if "batched_f16" in results else forms[-1]
-    hp = plans[head.split("_")[1]]
-    # the headline form's launch settings (a later form may have changed the plan's flags)
-    hp.set_flags(GRAPH | (PERSISTENT if hp.info()["persist_blocks"] else 0) |
-                 (FUSED_GH if results[head]["one_pass"] else 0))
-    log("[bench] %s: forward, adjoint and PDFB iterations" % head)
-    extras = time_extras(hp, x, xt, hp.to_plan(v_init), y_plan[head.split("_")[1]], eps, args.steps, args.warmup,
-                         dev)
     # (not in counter runs: their only large copy must be the calibration copy)
-    copy_gbs = None if args.calib_copy_mib else stream_copy_gbs(dev)
-    log("[bench] extras %s, stream copy %s GB/s" % (extras, copy_gbs))
-    if "batched_kb" in results and "batched_f16" in results:
-        results["batched_kb"]["speedup_vs_batched_f16"] = (results["batched_f16"]["ms_per_step"] /
-                                                           results["batched_kb"]["ms_per_step"])
-    r = results[head]
-    info = r["info"]
-    # dominant G kernel: gather, scatter, or the fused pass (which moves the
-    # gather's algorithmic bytes: G once, metadata, v and y in, c out)
-    cand = {k_: r["stage_ms"].get(k_, 0.0) for k_ in ("gather", "scatter", "dual_gs")}
-    dom = max(cand, key=cand.get)
-    alg = info["alg_bytes_scatter"] if dom == "scatter" else info["alg_bytes_gather"]
-    dur = cand[dom] * 1e-3
-    achieved = alg / dur / 1e9
+    rates = None if args.calib_copy_mib else stream_rates(dev)
+    log("[bench] streaming rates %s" % rates)
+
+    alg = stage_alg_bytes(info, L, Nc, Kc)
+    workload = args.config if not args.channels else "%s_%dch" % (args.config, L)
+    stages_tab = {}
+    for k_, t_ in r["stage_ms"].items():
+        if k_ not in alg or t_ <= 0:
+            continue
+        a_ = alg[k_]
+        tr = traffic_for(workload, k_)
+        stages_tab[k_] = {"ms": t_, "alg_bytes": a_, "alg_GBs": a_ / (t_ * 1e-3) / 1e9,
+                          "frac": a_ / (t_ * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "traffic": tr, "frac_physical": None if tr is None else tr / (t_ * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    dom = max(stages_tab, key=lambda k_: stages_tab[k_]["ms"])
+    d = stages_tab[dom]
     line = {
         "metric": METRIC,
         "value": r["vis_per_s"],
@@ -526,48 +594,47 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "%s: %d channels x %s blocks, %dx%d image (%dx%d grid), %d visibilities, "
-                               "w-stencils %d..%d, 30 dB" % (args.config, L, sorted(set(prob.n_blocks)),
-                                                              prob.Ny, prob.Nx, prob.Ky, prob.Kx, M,
-                                                              int(S.min()), int(S.max())),
-                   "g_source": "device builder" if args.device_g else "host windows",
-                   "form": head.replace("_", " ") + " (hipGraph)", "g_storage": head.split("_")[1],
-                   "taps": int(info["n_taps"])},
+                               "windows %d..%d, 30 dB" % (workload, L, sorted(set(prob.n_blocks)),
+                                                          prob.Ny, prob.Nx, prob.Ky, prob.Kx, M,
+                                                          int(S.min()), int(S.max())),
+                   "g_source": "device builder" if device_g else "host windows",
+                   "form": head.replace("_", " ") + " (hipGraph)" + (", one pass over G" if r["one_pass"] else ""),
+                   "g_storage": hprec, "taps": int(info["n_taps"])},
         "hbm_alg_GBs": r["alg_GBs"],
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic_for(dom, alg), "alg_bytes_per_launch": alg,
-                     "avg_launch_ms": dur * 1e3,
-                     # the one-pass stage is one launch per pitch class; its bytes
-                     # and time are per step (the sum over those launches)
+        "step_alg_bytes": r["alg_bytes_step"],
+        "step_frac": r["hbm_frac"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": d["frac"], "traffic": d["traffic"],
+                     "frac_physical": d["frac_physical"], "alg_bytes_per_launch": d["alg_bytes"],
+                     "avg_launch_ms": d["ms"],
+                     # the one-pass stage is one launch per pitch class; its bytes and
+                     # time are per step (the sum over those launches)
                      "launches_per_step": info["pitch_classes"] if dom == "dual_gs" else 1,
-                     "stream_copy_GBs": copy_gbs,
-                     "frac_of_stream_copy": achieved / copy_gbs if copy_gbs else None},
-        "forward_ms": extras["forward_ms"], "adjoint_ms": extras["adjoint_ms"],
-        "pdfb": dict(extras["pdfb"], primal_frac=extras["pdfb"]["primal_GBs"] / HBM_PEAK_GBS),
-        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "info"} for k, v in results.items()},
+                     "stream_copy_GBs": rates and rates["copy_GBs"], "stream_read_GBs": rates and rates["read_GBs"]},
+        "stages": stages_tab,
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk not in ("info", "graph_flags")}
+                  for k, v in results.items()},
+        "g_builder_s": gb_build if device_g else None,
     }
-    two = "twopass_" + head.split("_")[1]
-    if two in results and two != head:
-        # the same step with gather and scatter as separate passes (G read
-        # twice): its dominant kernel against the same peak
-        r2 = results[two]
-        c2 = {k_: r2["stage_ms"].get(k_, 0.0) for k_ in ("gather", "scatter")}
-        d2 = max(c2, key=c2.get)
-        a2 = info["alg_bytes_scatter"] if d2 == "scatter" else info["alg_bytes_gather"]
-        ach2 = a2 / (c2[d2] * 1e-3) / 1e9
-        line["roofline_two_pass"] = {"bound": "hbm", "kernel": d2, "achieved": ach2, "peak": HBM_PEAK_GBS,
-                                     "unit": "GB/s", "frac": ach2 / HBM_PEAK_GBS, "traffic": traffic_for(d2, a2),
-                                     "alg_bytes_per_launch": a2, "avg_launch_ms": c2[d2],
-                                     "ms_per_step": r2["ms_per_step"],
-                                     "frac_of_stream_copy": ach2 / copy_gbs if copy_gbs else None}
+    line.update(line_extra)
     if "plain_c64" in results:
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
-    if args.dr:
-        line["dimensionality_reduction"] = line_dr
-    if line_gb:
-        line["g_builder"] = line_gb
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"], line["err_vs_fp64_" + head] = cpu_baseline(prob, hp, theta)
+    if cpu is not None:
+        outs = cpu.results()
+        ref = [o for o in outs if o["l"] == cpu.chans[0]][0]
+        mtot = sum(o["M"] for o in outs)
+        tmax = max(o["s"] for o in outs)
+        line["cpu_baseline"] = {
+            "value": mtot / tmax, "unit": "visibilities/s", "cores": len(outs), "kind": "oracle",
+            "sample": "%d whole channel(s) %s of the same workload (%d visibilities each, %dx%d grid), one FP64 "
+                      "oracle dual step per channel, each in its own process (numpy.fft and scipy.sparse, "
+                      "single-threaded per process), started together; slowest %.1f s" % (
+                          len(outs), cpu.chans, outs[0]["M"], prob.Ky, prob.Kx, tmax),
+            "host": cpu.host}
+        line["err_vs_fp64"] = {f: rel_err(g, ref) for f, g in samples.items()}
+        line["err_vs_fp64"]["sample"] = "channel 0 (all its blocks): the oracle's inputs (x~ = x/2, v ~ 0.1 CN, " \
+                                        "y at 30 dB) through each form's plan and launch flags"
+        line["vs_cpu_baseline"] = r["vis_per_s"] / line["cpu_baseline"]["value"]
     print(json.dumps(line), flush=True)
 
 

@@ -16,6 +16,7 @@
 // per tile partial and merged in a fixed order, so results are bitwise
 // reproducible run to run.
 #include <hip/hip_fp16.h>
+#include <cstdlib>
 #include <hip/hip_runtime.h>
 
 #include "phi_internal.h"
@@ -383,11 +384,11 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
 // with conjugate twiddles.
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__ half, float2* __restrict__ grid,
-                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0, int pb,
+                                                      int np) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
-  const int np = Kx / W;
-  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  const int n1 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
   const float2* in = half + (size_t)l * Ny * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
@@ -405,11 +406,10 @@ __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__
 
 template <int N1, int N2, int W, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, const float2* __restrict__ tw, int Kx,
-                                                  int l0) {
+                                                  int l0, int pb, int np) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N1 * W];
-  const int np = Kx / W;
-  const int k2 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  const int k2 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
   float2* g = grid + (size_t)l * N * Kx + (size_t)k2 * Kx;
   for (int e = threadIdx.x; e < N1 * W; e += NT) {
     const int j = e / W, c = e % W;
@@ -431,11 +431,11 @@ __global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, con
 
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__ grid, float2* __restrict__ half,
-                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0, int pb,
+                                                      int np) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
-  const int np = Kx / W;
-  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  const int n1 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
   const float2* in = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int k2 = e / W, c = e % W;
@@ -1941,11 +1941,40 @@ constexpr int col_split1() {
 // panels in the second pass measured slower).
 constexpr int kColW2 = 32;
 
+// Column slabs of the two-pass transform: with slabs, both passes run on one
+// slab of columns of one channel before the next slab starts, so the second
+// pass reads what the first wrote while it is still in the memory-side cache
+// (256 MB on MI355X; a slab of 2048 columns of an 8192-row grid is 134 MB).
+// Environment PHI_COL_SLAB (columns, a multiple of 256; 0 = whole grid),
+// read once.
+static int col_slab_cols() {
+  static const int v = [] {
+    const char* e = std::getenv("PHI_COL_SLAB");
+    return e ? std::atoi(e) : 0;
+  }();
+  return v;
+}
+
 template <int N1, int N2, bool INV>
-hipError_t colfft2_pass_b(float2* grid, const float2* tw, int Kx, int l0, int nl, hipStream_t s) {
+hipError_t colfft2_pass_b(float2* grid, const float2* tw, int Kx, int l0, int nl, int pb, int np, hipStream_t s) {
   constexpr int W = kColW2, T = panel_threads<N1 * W>();
-  hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, T, INV>), dim3(N2 * (Kx / W), nl), dim3(T), 0, s, grid, tw, Kx, l0);
+  hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, T, INV>), dim3(N2 * np, nl), dim3(T), 0, s, grid, tw, Kx, l0, pb, np);
   return hipGetLastError();
+}
+
+// Panel ranges [pb, pb + np) and channel ranges of the two-pass transform:
+// the whole grid of every channel in one launch per pass, or slab by slab.
+template <typename F>
+static hipError_t colfft2_slabs(int Kx, int W, int l0, int nl, F&& run) {
+  const int np_all = Kx / W, slab = col_slab_cols();
+  const int np_slab = slab > 0 && slab % (8 * W) == 0 && slab < Kx && Kx % slab == 0 ? slab / W : np_all;
+  if (np_slab == np_all) return run(l0, nl, 0, np_all);
+  for (int l = l0; l < l0 + nl; ++l)
+    for (int pb = 0; pb < np_all; pb += np_slab) {
+      const hipError_t e = run(l, 1, pb, np_slab);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
 }
 
 template <int N>
@@ -1956,9 +1985,13 @@ hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int 
     constexpr int N2 = N / N1, W = kColW2;
     if (Kx % W == 0) {
       constexpr int TA = panel_threads<N2 * W>();
-      hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, half, grid, tw,
-                         Ny, Kx, l0);
-      return colfft2_pass_b<N1, N2, false>(grid, tw, Kx, l0, nl, s);
+      return colfft2_slabs(Kx, W, l0, nl, [&](int la, int nla, int pb, int np) {
+        hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, TA>), dim3(N1 * np, nla), dim3(TA), 0, s, half, grid, tw, Ny,
+                           Kx, la, pb, np);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        return colfft2_pass_b<N1, N2, false>(grid, tw, Kx, la, nla, pb, np, s);
+      });
     }
   }
   constexpr int W = col_width<N>();
@@ -1978,11 +2011,13 @@ hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int 
       // the pass along k1 runs in place on the grid, which the adjoint no
       // longer needs afterwards
       constexpr int TA = panel_threads<N2 * W>();
-      const hipError_t e = colfft2_pass_b<N1, N2, true>(const_cast<float2*>(grid), tw, Kx, l0, nl, s);
-      if (e != hipSuccess) return e;
-      hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, grid, half, tw,
-                         Ny, Kx, l0);
-      return hipGetLastError();
+      return colfft2_slabs(Kx, W, l0, nl, [&](int la, int nla, int pb, int np) {
+        const hipError_t e = colfft2_pass_b<N1, N2, true>(const_cast<float2*>(grid), tw, Kx, la, nla, pb, np, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, TA>), dim3(N1 * np, nla), dim3(TA), 0, s, grid, half, tw, Ny,
+                           Kx, la, pb, np);
+        return hipGetLastError();
+      });
     }
   }
   constexpr int W = col_width<N>();

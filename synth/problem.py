@@ -26,12 +26,19 @@ Recipes (stand-ins for the VLA Cyg A data of Section 5, which is not used):
 from dataclasses import dataclass, field
 
 import numpy as np
-from scipy.ndimage import gaussian_filter
+from scipy.ndimage import fourier_gaussian, gaussian_filter
 
 from .kb import KB_J, kb_beta, kb_psi, deapodisation, window_base
 from .windows import windows_c, windows_numpy, SD_MAX
 
 ROOT_SEED = 220907604
+
+
+def _smooth(a, sigma):
+    """Periodic Gaussian smoothing (standard deviation sigma pixels) through
+    the FFT: seconds at 4096^2, where a direct 8-sigma-wide filter is not."""
+    Ny, Nx = a.shape
+    return np.fft.irfft2(fourier_gaussian(np.fft.rfft2(a), sigma, n=Nx), s=(Ny, Nx))
 
 
 @dataclass
@@ -47,6 +54,9 @@ class Block:
     _skw: np.ndarray = field(repr=False, default=None)
     _uy: np.ndarray = field(repr=False, default=None)
     _ux: np.ndarray = field(repr=False, default=None)
+    _taps: object = field(repr=False, default=None)   # builds (_uy, _ux) on first use
+    w_h: np.ndarray = field(repr=False, default=None)    # [M] w-kernel half-width h (cells)
+    w_a: np.ndarray = field(repr=False, default=None)    # [M] w-chirp parameter (cells)
     _pair_id: np.ndarray = field(repr=False, default=None)
     _pairs: np.ndarray = field(repr=False, default=None)
     _pair_sd: np.ndarray = field(repr=False, default=None)
@@ -58,6 +68,8 @@ class Block:
     def windows(self, dtype=np.complex128, engine="c"):
         """(flat windows, offsets[M+1]); window m is S[m] x S[m] row-major,
         entry (i, j) multiplies grid cell ((base_y+i) mod Ky, (base_x+j) mod Kx)."""
+        if self._uy is None and self._taps is not None:
+            self._uy, self._ux = self._taps()
         if engine == "numpy":
             w, off, S = windows_numpy(self._skw, self._uy, self._ux, self._pair_id,
                                       self._pairs, self._pair_sd)
@@ -122,7 +134,7 @@ class Problem:
         cache = self.__dict__.setdefault("_sky_cache", {})
         if "alpha" not in cache:
             rng = self.rng(10_001)
-            a = gaussian_filter(rng.standard_normal((self.Ny, self.Nx)), max(2.0, self.Ny / 16))
+            a = _smooth(rng.standard_normal((self.Ny, self.Nx)), max(2.0, self.Ny / 16))
             a = (a - a.min()) / max(a.max() - a.min(), 1e-30)
             cache["alpha"] = 0.5 + 0.5 * a
         return cache["alpha"]
@@ -137,7 +149,7 @@ class Problem:
         np.add.at(x, (py, px), flux)
         if self.blob:
             sig = max(1.0, 8.0 * min(Ny, Nx) / 256.0)
-            noise = gaussian_filter(rng.standard_normal((Ny, Nx)), sig)
+            noise = _smooth(rng.standard_normal((Ny, Nx)), sig)
             noise = np.clip(noise, 0.0, None)
             yy, xx = np.meshgrid(np.arange(Ny) - Ny / 2, np.arange(Nx) - Nx / 2, indexing="ij")
             ay, ax = 0.3 * Ny, 0.2 * Nx
@@ -198,29 +210,37 @@ class Problem:
             cache[l] = self._channel_uv_draw(l)
         return cache[l]
 
+    def _ref_uv(self):
+        """The reference (omega, w) draw that wideband channels scale."""
+        cache = self.__dict__.setdefault("_ref_uv_cache", {})
+        if "ref" not in cache:
+            rng = self.rng(20_000)
+            Mref = max(int(sum(m)) for m in self.n_vis)
+            if self.coverage == "tracks":
+                om = self._track_omega(Mref)
+            else:
+                om = self._gauss_omega(rng, Mref)
+            cache["ref"] = (om, rng.uniform(0.0, 1.0, Mref))
+        return cache["ref"]
+
     def _channel_uv_draw(self, l):
         Ml = int(sum(self.n_vis[l]))
-        if self.coverage == "tracks":
-            rng = self.rng(20_000)
-            Mref = max(int(sum(m)) for m in self.n_vis)
-            om = self._track_omega(Mref)[:Ml]
-            w = rng.uniform(0.0, 1.0, Mref)[:Ml]
+        if self.coverage == "tracks" or self.shared_uv:
+            om_ref, w_ref = self._ref_uv()
             scale = self.nu[l] / self.nu.max() if self.nu is not None else 1.0
-            om = om * scale
-            w = w * scale
-        elif self.shared_uv:
-            rng = self.rng(20_000)
-            Mref = max(int(sum(m)) for m in self.n_vis)
-            om = self._gauss_omega(rng, Mref)[:Ml]
-            w = rng.uniform(0.0, 1.0, Mref)[:Ml]
-            scale = self.nu[l] / self.nu.max() if self.nu is not None else 1.0
-            om = om * scale
-            w = w * scale
+            om = om_ref[:Ml] * scale
+            w = w_ref[:Ml] * scale
+            # blocks split by |omega| quantiles of the reference draw (the
+            # channel's draw is that draw scaled by one positive factor)
+            cache = self.__dict__.setdefault("_ref_uv_cache", {})
+            if ("order", Ml) not in cache:
+                cache[("order", Ml)] = np.argsort(np.hypot(om_ref[:Ml, 0], om_ref[:Ml, 1]), kind="stable")
+            order = cache[("order", Ml)]
         else:
             rng = self.rng(20_001, l)
             om = self._gauss_omega(rng, Ml)
             w = rng.uniform(0.0, 1.0, Ml)
-        order = np.argsort(np.hypot(om[:, 0], om[:, 1]), kind="stable")
+            order = np.argsort(np.hypot(om[:, 0], om[:, 1]), kind="stable")
         bounds = np.concatenate([[0], np.cumsum(self.n_vis[l])])
         groups = []
         rng2 = self.rng(20_002, l)
@@ -297,33 +317,38 @@ class Problem:
         h = np.minimum(h, hmax)
         skw = (KB_J + 2 * h).astype(np.int32)
         S = (skw + sd - 1).astype(np.int32)
-        ldu = int(skw.max()) if M else 1
-        uy = np.zeros((M, ldu), dtype=np.complex128)
-        ux = np.zeros((M, ldu), dtype=np.complex128)
         by_kb = window_base(kap_y, KB_J)
         bx_kb = window_base(kap_x, KB_J)
-        taps = np.arange(KB_J)
-        psi_y = kb_psi(kap_y[:, None] - (by_kb[:, None] + taps), KB_J, beta)
-        psi_x = kb_psi(kap_x[:, None] - (bx_kb[:, None] + taps), KB_J, beta)
         a_eff = np.where(np.round(a) > h, h.astype(np.float64), a)
-        for hv in np.unique(h):
-            sel = np.nonzero(h == hv)[0]
-            n = KB_J + 2 * int(hv)
-            if hv == 0:
-                uy[sel, :KB_J] = psi_y[sel]
-                ux[sel, :KB_J] = psi_x[sel]
-                continue
-            wk = self._wkernel_batch(a_eff[sel], int(hv))      # [Mg, 2hv+1]
-            for t in range(2 * int(hv) + 1):
-                uy[sel, t:t + KB_J] += psi_y[sel] * wk[:, t:t + 1]
-                ux[sel, t:t + KB_J] += psi_x[sel] * wk[:, t:t + 1]
+
+        def taps():
+            # per-axis tap vectors: the Kaiser-Bessel taps convolved with the
+            # w-kernel (built only when the windows themselves are asked for)
+            ldu = int(skw.max()) if M else 1
+            uy = np.zeros((M, ldu), dtype=np.complex128)
+            ux = np.zeros((M, ldu), dtype=np.complex128)
+            t = np.arange(KB_J)
+            psi_y = kb_psi(kap_y[:, None] - (by_kb[:, None] + t), KB_J, beta)
+            psi_x = kb_psi(kap_x[:, None] - (bx_kb[:, None] + t), KB_J, beta)
+            for hv in np.unique(h):
+                sel = np.nonzero(h == hv)[0]
+                if hv == 0:
+                    uy[sel, :KB_J] = psi_y[sel]
+                    ux[sel, :KB_J] = psi_x[sel]
+                    continue
+                wk = self._wkernel_batch(a_eff[sel], int(hv))      # [Mg, 2hv+1]
+                for k in range(2 * int(hv) + 1):
+                    uy[sel, k:k + KB_J] += psi_y[sel] * wk[:, k:k + 1]
+                    ux[sel, k:k + KB_J] += psi_x[sel] * wk[:, k:k + 1]
+            return uy, ux
+
         # window bases: w-kernel widens by h, DDE kernel by (sd-1)/2 on each side
         ext = h + (sd - 1) // 2
         by = by_kb - ext
         bx = bx_kb - ext
         base = np.stack([np.mod(by, Ky), np.mod(bx, Kx)], axis=1).astype(np.int32)
         blk = Block(l=l, b=b, Ky=Ky, Kx=Kx, omega=om, w=w, S=S, base=base,
-                    _skw=skw, _uy=uy, _ux=ux, _pair_id=pair_id, _pairs=tab, _pair_sd=pair_sd)
+                    _skw=skw, _taps=taps, w_h=h.astype(np.int32), w_a=a_eff, _pair_id=pair_id, _pairs=tab, _pair_sd=pair_sd)
         return blk
 
 

@@ -1,6 +1,8 @@
 """Long grid columns (Ky = 3072 ... 8192): the column transforms of these
-lengths run in two passes (N = N1 N2); long rows (Kx = 4096, 8192) run with
-512 threads per row.  Tall, narrow images keep the FP64 oracle
+lengths run in two passes (N = N1 N2); long rows (Kx = 3072 ... 8192) run as
+half-length complex transforms with radix-3 and radix-5 passes where the
+length has those factors (3072 = 3 2^10, 5120 = 5 2^10, 6144 = 3 2^11) and
+192 ... 512 threads per row.  Tall, narrow images keep the FP64 oracle
 cheap while the column length is that of the 4096^2-image workloads.
 Forward, adjoint and the dual step against the oracle at the FP32 bound."""
 import sys
@@ -23,8 +25,9 @@ def _say(*a):
 # (Ny, Nx): Ky = 2 Ny (image edges are multiples of 16, so Kx is a multiple
 # of 32 and every such plan takes the two-pass transform)
 SHAPES = [(1536, 16), (2048, 16), (2560, 16), (3072, 16), (4096, 16), (4096, 32),
-          # long rows (Kx = 4096, 8192): row transforms with 512 threads
-          (16, 2048), (16, 4096)]
+          # long rows: Kx = 3072 (radix 3), 4096, 5120 (radix 5, the 1536 x 2560
+          # image's rows), 6144 (radix 3), 8192
+          (16, 1536), (16, 2048), (16, 2560), (16, 3072), (16, 4096)]
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES)

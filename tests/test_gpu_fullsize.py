@@ -1,15 +1,22 @@
 """Full-size parity: the 16-channel x 4-block, 1024^2, 1.5M-visibility-per-channel
-workload (w-stencils 7..17) in the launch configuration bench.py times
-(batched, hipGraph replay, tile 16), checked against the FP64 oracle on every
-output of two whole channels (the lowest and highest frequency): v+, grad,
-rho and r of all their blocks.  Complex64 G must match to 1e-5, FP16 G to 2e-3.
+workload (w-stencils 7..17), checked against the FP64 oracle on every output of
+two whole channels (the lowest and highest frequency): v+, grad, rho and r of
+all their blocks.
+
+Launch forms: the two passes over G at tile 16 (complex64 and FP16), the
+autotuned batched form replayed from a hipGraph (what bench.py times: one pass
+over G launched per pitch class when the autotuner picks it), and the one pass
+forced on a persistent grid (each work-group runs many items and prefetches the
+next one's grid region).  Complex64 G must match to 1e-5; FP16 G to 2e-3
+against the FP64 G and to 1e-5 against the oracle run on the same rounded G;
+BF16 G to 1e-5 against its rounded G, its error against FP64 G is reported.
 """
 import sys
 
 import numpy as np
 import pytest
 
-from _cases import rel_l2
+from _cases import rel_l2, quantise
 
 pytestmark = pytest.mark.gpu
 
@@ -72,26 +79,41 @@ def full():
     return dict(prob=prob, blocks=blocks, exact=exact, theta=theta, ops=ops, Y=Y, V=V, eps=eps, s_y=s_y, s_x=s_x)
 
 
-def _oracle_dual(F, l):
+def _oracle_dual(F, l, gprec=None):
+    """The oracle's dual step on channel l, with G exact (gprec None) or
+    rounded to the plan's storage first."""
     import oracle
     prob, exact, theta = F["prob"], F["exact"], F["theta"]
     ks = F["ops"][l][0]
     op = oracle.Operator(prob.Ny, prob.Nx, F["s_y"], F["s_x"],
-                         [oracle.BlockG(l, theta[k], oracle.g_matrix(exact[k][0].base, exact[k][0].S, exact[k][1],
-                                                                     exact[k][2], prob.Ky, prob.Kx, theta[k]))
+                         [oracle.BlockG(l, theta[k], oracle.g_matrix(
+                             exact[k][0].base, exact[k][0].S,
+                             exact[k][1] if gprec is None else quantise(exact[k][1], gprec),
+                             exact[k][2], prob.Ky, prob.Kx, theta[k]))
                           for k in ks])
     Xt = {l: 0.5 * prob.image(l).astype(np.float64)}
     return ks, oracle.dual_step(op, Xt, [F["V"][k] for k in ks], [F["Y"][k] for k in ks], F["eps"][ks])
 
 
-@pytest.fixture(scope="module")
-def oracle_results(full):
-    return {l: _oracle_dual(full, l) for l in CHECK}
+_ORACLE = {}
 
 
-@pytest.mark.parametrize("prec,tol", [("c64", 1e-5), ("f16", 2e-3)])
-def test_fullsize_dual_step(full, oracle_results, prec, tol):
-    from paper_2209_07604_amd import Plan, GRAPH
+def oracle_result(F, l, gprec=None):
+    if (l, gprec) not in _ORACLE:
+        _say("[fullsize] oracle channel", l, "G", gprec or "fp64")
+        _ORACLE[(l, gprec)] = _oracle_dual(F, l, gprec)
+    return _ORACLE[(l, gprec)]
+
+
+# (G storage, launch form, bound against the FP64 G, bound against the rounded G)
+FORMS = [("c64", "twopass", 1e-5, None), ("f16", "twopass", 2e-3, 1e-5), ("f16", "headline", 2e-3, 1e-5),
+         ("f16", "fused_persistent", 2e-3, 1e-5), ("bf16", "headline", None, 1e-5)]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec,form,tol,tol_q", FORMS)
+def test_fullsize_dual_step(full, prec, form, tol, tol_q):
+    from paper_2209_07604_amd import Plan, GRAPH, FUSED_GH, PERSISTENT
     prob, blocks = full["prob"], full["blocks"]
     n_vis = [len(S) for (_, S, _) in blocks]
     base = np.concatenate([b for (b, _, _) in blocks])
@@ -100,8 +122,19 @@ def test_fullsize_dual_step(full, oracle_results, prec, tol):
                 g_prec=prec, flags=GRAPH)
     for k, (_, _, w) in enumerate(blocks):
         plan.load_g(k, w)
-    plan.set_tuning(16, 0)
-    _say("[fullsize] plan", prec, plan.info())
+    if form == "twopass":
+        plan.set_tuning(16, 0)
+    elif form == "headline":
+        # bench.py's batched form: autotuned tile / launch shape / pass count,
+        # replayed from a hipGraph
+        plan.autotune(3)
+        i = plan.info()
+        plan.set_flags(GRAPH | (PERSISTENT if i["persist_blocks"] else 0) | (FUSED_GH if i["fused"] else 0))
+    else:
+        plan.set_tuning(16, 1024)
+        plan.set_flags(GRAPH | PERSISTENT | FUSED_GH)
+        assert plan.info()["fused"] == 1 and plan.info()["n_items"] > 1024
+    _say("[fullsize] plan", prec, form, plan.info())
     xt = torch.from_numpy(np.stack([0.5 * prob.image(l) for l in range(prob.L)]).astype(np.float32)).cuda()
     v = plan.to_plan(torch.from_numpy(np.concatenate(full["V"]).astype(np.complex64)).cuda())
     y = plan.to_plan(torch.from_numpy(np.concatenate(full["Y"]).astype(np.complex64)).cuda())
@@ -114,13 +147,19 @@ def test_fullsize_dual_step(full, oracle_results, prec, tol):
     rho, res = rho.cpu().numpy(), res.cpu().numpy()
     starts = np.concatenate([[0], np.cumsum(n_vis)])
     for l in CHECK:
-        ks, (Vp_o, grad_o, rho_o, res_o) = oracle_results[l]
-        got_v = np.concatenate([vp[starts[k]:starts[k + 1]] for k in ks])
-        e_v = rel_l2(got_v, np.concatenate(Vp_o))
-        e_g = rel_l2(grad[l], grad_o[l])
-        e_rho = rel_l2(rho[ks], rho_o)
-        e_res = rel_l2(res[ks], res_o)
-        _say("[fullsize] %s channel %d: rel L2 v+ %.2e grad %.2e rho %.2e res %.2e (rho/eps %s)" % (
-            prec, l, e_v, e_g, e_rho, e_res, np.round(rho_o / full["eps"][ks], 2)))
-        assert np.all(rho_o > full["eps"][ks])
-        assert e_v <= tol and e_g <= tol and e_rho <= tol and e_res <= tol
+        checks = [(None, tol)] + ([(prec, tol_q)] if prec != "c64" else [])
+        for gq, bound in checks:
+            ks, (Vp_o, grad_o, rho_o, res_o) = oracle_result(full, l, gq)
+            got_v = np.concatenate([vp[starts[k]:starts[k + 1]] for k in ks])
+            e_v = rel_l2(got_v, np.concatenate(Vp_o))
+            e_g = rel_l2(grad[l], grad_o[l])
+            e_rho = rel_l2(rho[ks], rho_o)
+            e_res = rel_l2(res[ks], res_o)
+            _say("[fullsize] %s %s channel %d vs oracle with %s G: rel L2 v+ %.2e grad %.2e rho %.2e res %.2e "
+                 "(rho/eps %s)" % (prec, form, l, gq or "FP64", e_v, e_g, e_rho, e_res,
+                                   np.round(rho_o / full["eps"][ks], 2)))
+            assert np.all(rho_o > full["eps"][ks])
+            if bound is not None:
+                assert e_v <= bound and e_g <= bound and e_rho <= bound and e_res <= bound
+            else:
+                assert e_v <= 1e-2    # BF16 against FP64 G: reported, sanity bound only

@@ -101,3 +101,65 @@ def test_fused_over_pitch_classes(prec, monkeypatch):
         _say("  grad ch", l, "vs oracle", e)
         assert e <= 1e-5
 
+
+
+@pytest.mark.parametrize("prec", ["f16", "c64"])
+def test_fused_persistent_grid(prec):
+    """A persistent grid smaller than the item count makes each work-group run
+    many items, so the one pass prefetches the next item's descriptor and grid
+    region while the current one runs.  v+ and the norms must equal the run
+    with one work-group per item bitwise, and grad to the last bit as well
+    (the merge order does not depend on the launch shape)."""
+    from test_gpu_parity import gpu_dual
+    from paper_2209_07604_amd import FUSED_GH, PERSISTENT, GRAPH
+    c = case("C2s")
+    plan = c.plan(g_prec=prec)
+    plan.set_tuning(16, 0)
+    plan.set_flags(FUSED_GH)
+    n_items = plan.info()["n_items"]
+    sigma = np.linspace(0.9, 1.1, len(c.blocks))
+    ref = gpu_dual(c, plan, c.V, c.eps, sigma)
+    for pb in (97, 1024):
+        plan.set_tuning(16, pb)
+        plan.set_flags(FUSED_GH | PERSISTENT | GRAPH)
+        info = plan.info()
+        _say("[fused persistent]", prec, "items", n_items, "grid", info["persist_blocks"])
+        assert info["fused"] == 1 and info["persist_blocks"] == pb and pb < n_items
+        got = gpu_dual(c, plan, c.V, c.eps, sigma)
+        assert all(np.array_equal(x, y) for x, y in zip(got[0], ref[0]))
+        assert np.array_equal(got[1], ref[1])
+        assert np.array_equal(got[2], ref[2]) and np.array_equal(got[3], ref[3])
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_nonfinite_norm_reported_once(fused):
+    """A NaN in one block's data makes that block's FP64 norm non-finite: the
+    dual step records it on the device, phi_plan_check reports
+    PHI_ERR_NONFINITE once and clears the flag, and a clean step afterwards
+    checks OK.  (Only the data is non-finite; every kernel runs normally.)"""
+    from paper_2209_07604_amd import FUSED_GH, PhiError
+    from paper_2209_07604_amd._lib import STATUS
+    c = case("C2s")
+    plan = c.plan(g_prec="f16")
+    plan.set_tuning(16, 0)
+    plan.set_flags(FUSED_GH if fused else 0)
+    assert plan.info()["fused"] == (1 if fused else 0)
+    xt = torch.from_numpy(c.cube(c.Xt)).cuda()
+    Y = [y.copy() for y in c.Y]
+    Y[2][5] = np.nan
+    y_bad = plan.to_plan(torch.from_numpy(c.flat(Y).astype(np.complex64)).cuda())
+    y_ok = plan.to_plan(torch.from_numpy(c.flat(c.Y).astype(np.complex64)).cuda())
+    v0 = plan.to_plan(torch.from_numpy(c.flat(c.V).astype(np.complex64)).cuda())
+    eps = torch.from_numpy(np.asarray(c.eps, np.float64)).cuda()
+    v = v0.clone()
+    _, rho, _ = plan.dual_step(xt, v, y_bad, eps)
+    with pytest.raises(PhiError) as ei:
+        plan.check()
+    assert STATUS[ei.value.code] == "PHI_ERR_NONFINITE"
+    r = rho.cpu().numpy()
+    assert not np.isfinite(r[2]) and np.all(np.isfinite(np.delete(r, 2)))
+    plan.check()                                   # the flag was cleared
+    v = v0.clone()
+    _, rho, _ = plan.dual_step(xt, v, y_ok, eps)
+    plan.check()
+    assert np.all(np.isfinite(rho.cpu().numpy()))
