@@ -310,6 +310,63 @@ def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
     return out
 
 
+def time_dr(p, x, xt, y, head, args, dev):
+    """The visibility-gridding reduction (Section 3.4) on plan p (created with
+    PHI_DR): device set-up time, then the reduced dual step (autotuned,
+    hipGraph) against the unreduced step on the same data; both forms' row and
+    byte counts, and the form the bytes rule keeps."""
+    import torch
+    from paper_2209_07604_amd import GRAPH, PERSISTENT, FUSED_GH
+    info = p.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    yred, m_red = p.dr_setup(y)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    rp = p.reduced()
+    rp.autotune(3)
+    ri = rp.info()
+    rp.set_flags(GRAPH | (PERSISTENT if ri["persist_blocks"] else 0) | (FUSED_GH if ri["fused"] else 0))
+    eps = torch.tensor([np.sqrt(m + 2.0 * np.sqrt(m)) for m in m_red], dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    mr = int(m_red.sum())
+    v0 = (0.1 * torch.complex(torch.randn(mr, generator=gen, device=dev),
+                              torch.randn(mr, generator=gen, device=dev))).contiguous()
+    v = v0.clone()
+    grad = torch.empty_like(xt)
+    rho = torch.empty(p.nblk, dtype=torch.float64, device=dev)
+    res = torch.empty_like(rho)
+    for _ in range(args.warmup):
+        p.dual_step_dr(xt, v, yred, eps, None, grad, rho, res)
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    ms = _event_ms(lambda: p.dual_step_dr(xt, v, yred, eps, None, grad, rho, res), args.steps)
+    rp.check()
+    rp.set_flags(0 | (PERSISTENT if ri["persist_blocks"] else 0) | (FUSED_GH if ri["fused"] else 0))
+    v.copy_(v0)
+    torch.cuda.synchronize()
+    rp.set_timing(True)
+    for _ in range(args.steps):
+        p.dual_step_dr(xt, v, yred, eps, None, grad, rho, res)
+    torch.cuda.synchronize()
+    rp.set_timing(False)
+    stages, calls = rp.get_timing()
+    M = int(info["n_vis_total"])
+    out = {"M": M, "M_reduced": mr, "M_over_M_reduced": M / mr, "taps_G": int(info["n_taps"]),
+           "taps_H": int(info["dr_taps"]), "bytes_G": int(info["g_bytes"]), "bytes_H": int(info["dr_bytes"]),
+           "largest_row_window": int(info["dr_max_window"]), "setup_ms": setup_ms,
+           "ms_per_step_reduced": ms, "ms_per_step_unreduced": head["ms_per_step"],
+           "visibilities_per_s_reduced": M / (ms * 1e-3), "tile": ri["tile"], "one_pass": bool(ri["fused"]),
+           "stage_ms": {k_: v_ / max(calls, 1) for k_, v_ in stages.items() if v_ > 0},
+           "kept": "reduced" if info["dr_bytes"] < info["g_bytes"] else "unreduced",
+           "rule": "keep the reduced form only if the rows of Lam H hold fewer bytes than G"}
+    out["speedup"] = head["ms_per_step"] / ms
+    log("[bench] reduced step: %s" % out)
+    del v, v0, grad, yred
+    return out
+
+
 def run_sample(p, prob, smp, theta, flags, dev):
     """The oracle's channel-0 inputs through plan p (other channels zero):
     (v+ channel 0 user order, grad channel 0, rho, res of channel 0's blocks)."""
@@ -365,6 +422,9 @@ def main():
     ap.add_argument("--host-g", action="store_true",
                     help="load G from host windows built by the generator instead of the device builder")
     ap.add_argument("--no-extras", action="store_true", help="skip forward/adjoint/PDFB timings")
+    ap.add_argument("--dr", action="store_true",
+                    help="also time the visibility-gridding reduced step (Section 3.4) on the headline plan, "
+                         "e.g. --config C5t (VLA-like tracks)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after timing, run one plain device copy of this size (HBM counter calibration)")
     args = ap.parse_args()
@@ -389,7 +449,7 @@ def main():
         log("[bench] cpu baseline: %d oracle process(es) on channels %s, host %s" % (nw, cpu.chans, cpu.host))
 
     import torch
-    from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH
+    from paper_2209_07604_amd import Plan, PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH, DR
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
@@ -434,7 +494,8 @@ def main():
     hp = None
     for prec in precs:
         tp = time.time()
-        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
+        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev,
+                 flags=DR if (args.dr and prec == hprec) else 0)
         tile0 = p.info()["tile"]
         log("[bench] plan %s created (%.1f s), workspace %.1f GB" % (prec, time.time() - tp, p.workspace_size() / 1e9))
         torch.cuda.synchronize()
@@ -548,6 +609,7 @@ def main():
     info = r["info"]
     hflags = r["graph_flags"]
     hp.set_flags(hflags)
+    line_dr = time_dr(hp, x, xt, hp_y, r, args, dev) if args.dr else None
     line_extra = {}
     if not args.no_extras:
         log("[bench] %s: forward, adjoint and PDFB iterations" % head)
@@ -617,6 +679,8 @@ def main():
         "g_builder_s": gb_build if device_g else None,
     }
     line.update(line_extra)
+    if line_dr:
+        line["dimensionality_reduction"] = line_dr
     if "plain_c64" in results:
         line["speedup_vs_plain_fp32"] = results["plain_c64"]["ms_per_step"] / r["ms_per_step"]
     if cpu is not None:

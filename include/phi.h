@@ -96,12 +96,15 @@ enum {
                            instead of one launch over all channels/blocks  */
   PHI_GRAPH = 2,        /* replay the dual step from a captured hipGraph    */
   PHI_PERSISTENT = 4,   /* G stages run as a persistent grid over work items */
-  PHI_FUSED_GH = 8      /* dual step in one pass over G (c and G^H theta c
+  PHI_FUSED_GH = 8,     /* dual step in one pass over G (c and G^H theta c
                            from the same taps; sigma * scale applied to v+
                            and in the merge) instead of a G pass and a G^H
                            pass; used with stored G where the item's grid
                            tile and one accumulator per wave fit a
                            work-group's LDS (e.g. 16-cell tiles)            */
+  PHI_DR = 16           /* at plan creation only: also build the plan of the
+                           visibility-gridding reduction (phi_dr_setup) in
+                           the same workspace; stored G only                */
 };
 
 typedef struct {
@@ -148,6 +151,14 @@ typedef struct {
                                   smallest up until a group holds 8192 items
                                   (environment PHI_PITCH_CLASS_ITEMS, read at
                                   phi_plan_create, overrides; >= 1)          */
+  /* plans created with PHI_DR: the reduced rows and their stored taps, to be
+     weighed against n_vis_total and n_taps (the reduction pays only when the
+     rows of Lam H hold fewer bytes than G)                                   */
+  int64_t dr_rows;             /* M' = sum_b |S_b| (0 without PHI_DR)        */
+  int64_t dr_taps;             /* sum over reduced rows of s^2               */
+  int64_t dr_bytes;            /* device bytes of the reduced rows           */
+  int32_t dr_max_window;       /* largest reduced-row window edge s          */
+  int32_t reduced;             /* 1 on the handle phi_dr_plan returns        */
 } phi_info;
 
 /* Validate `desc`, sort visibilities and build the work lists (host only,
@@ -385,30 +396,60 @@ phi_status phi_pdfb_run(phi_plan plan, float* d_x, float* d_xt, void* d_v, const
                         void* stream);
 
 /* ---------------------------------------------------------------------------
- * Visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5) of one
- * data block, computed on the host in FP64 (a plan-time step, like packing G):
- *   H = G^H Theta^H Theta G, S = {p : H_pp > 0}, Lam_p = H_pp^(-1/2),
- *   y' = Lam G^H Theta^H y, Phi' = Lam H F Z.
- * Row p of Lam H is returned as a dense W x W window (W = 2 Smax - 1,
- * Smax = largest window of the block, which must be <= 11) anchored at
- * (p_y - Smax + 1, p_x - Smax + 1) mod K, rows sorted by cell index
- * p = p_y * Kx + p_x.  Because H is Hermitian, (Lam H)^H = H Lam: feeding
- * these windows, theta = 1 and y' to an ordinary plan gives Phi', its
- * adjoint and the reduced dual step (with eps'^2 = M' + 2 sqrt(M')).
- * Inputs are one block's arrays in the layout of phi_desc / phi_plan_load_g;
- * h_y (complex128 [n_vis]) may be NULL (then y' = 0).  Host memory only.
+ * Visibility-gridding dimensionality reduction (Section 3.4, eqs. 4-5), per
+ * data block b with whitening theta_b, computed on the device from the
+ * plan's stored G:
+ *   H = G^H Theta^H Theta G (Hermitian), S_b = {p : H_pp > 0} (M'_b cells),
+ *   Lam_p = H_pp^(-1/2) on S_b, y' = Lam G^H Theta^H y, Phi' = Lam H F Z,
+ * and the l2 ball of the reduced data has radius eps' (the caller's choice,
+ * e.g. eps'^2 = M' + 2 sqrt(M'), the chi-square rule with M' points).
+ *
+ * A plan created with PHI_DR computes, at creation and on the host, the
+ * support of every block (the cells its windows cover) and, for every
+ * support cell p, the window of row p of Lam H: the smallest odd square
+ * holding every window that covers p (edge s from S to 2 S - 1).  Those rows
+ * form the reduced plan: same channels, blocks and theta, M'_b rows per
+ * block, stored in the plan's precision.  Creation fails with
+ * PHI_ERR_UNSUPPORTED where a row's window would exceed 21 x 21 (dense
+ * coverage with S > 11) or the grid is smaller than 42 cells; with
+ * PHI_ERR_ARG for g_prec = PHI_G_KB.  phi_plan_workspace_size then covers
+ * both plans, which share the grid buffers (calls on the two must not
+ * overlap), and phi_plan_get_info reports M', the reduced taps and bytes.
+ * Reduced-order vectors hold the rows in the reduced plan's order.
  */
-typedef struct phi_dr_s* phi_dr;
-phi_status phi_dr_create(int32_t ky, int32_t kx, int64_t n_vis, const int32_t* h_base, const uint8_t* h_stencil,
-                         const void* h_windows, int32_t host_type, double theta, const void* h_y, phi_dr* out);
-/* M' (reduced rows) and W (their window edge). */
-phi_status phi_dr_size(phi_dr dr, int64_t* n_red, int32_t* w);
-/* Copy the reduced block: bases [M'][2], window sizes [M'] (= W), windows
- * complex128 [M'][W*W], y' complex128 [M'], Lam [M'], cell [M'].  Any output
- * pointer may be NULL. */
-phi_status phi_dr_copy(phi_dr dr, int32_t* h_base, uint8_t* h_stencil, void* h_windows, void* h_y, double* h_lam,
-                       int64_t* h_cell);
-phi_status phi_dr_destroy(phi_dr dr);
+
+/* Row values and gridded data (the device set-up of the reduction).  The
+ * plan must be bound with every block's G loaded.  Row p of Lam H is
+ * theta_b Lam0_p (H0)_pq with H0 = G^H G and Lam0 = H0_pp^(-1/2): the rows
+ * store Lam0 H0 (rounded once to the plan's precision) and the reduced plan
+ * applies theta_b; y' = Lam0 G^H y.  Sums run in FP64 in a fixed order
+ * (windows covering p in plan order).  d_y: complex64 [M_tot] plan order
+ * (NULL: y' = 0); d_yred: complex64 [M'] reduced order, out; h_m_red: host
+ * int64 [sum B] out, M'_b (may be NULL).  Asynchronous on `stream`.
+ * PHI_ERR_STATE without PHI_DR, unbound or with G not loaded. */
+phi_status phi_dr_setup(phi_plan plan, const void* d_y, void* d_yred, int64_t* h_m_red, void* stream);
+
+/* The reduced data-fidelity dual step: l2ball_dual_step of Phi' on the
+ * reduced plan (same arguments and semantics with M' rows: d_vred and
+ * d_yred complex64 [M'] reduced order, d_eps_red and d_sigma [sum B];
+ * grad_l = sum_b Re Phi'_{l,b}^dagger v'+_b).  PHI_ERR_STATE before
+ * phi_dr_setup. */
+phi_status l2ball_dual_step_dr(phi_plan plan, const float* d_xt, void* d_vred, const void* d_yred,
+                               const double* d_eps_red, const double* d_sigma, float* d_grad, double* d_rho,
+                               double* d_res, void* stream);
+
+/* The reduced plan as a handle owned by `plan` (destroyed with it; it is not
+ * bound, destroyed or loaded on its own: those calls return PHI_ERR_STATE).
+ * Every other call applies to it: phi_forward is Phi', phi_adjoint
+ * Re Phi'^dagger, phi_plan_autotune, phi_plan_set_flags and timing tune and
+ * time the reduced step, phi_plan_read_g reads its rows. */
+phi_status phi_dr_plan(phi_plan plan, phi_plan* reduced);
+
+/* Host copies, in reduced order, of each row's cell p = p_y Kx + p_x
+ * (h_cells, int64 [M']), its window origin (h_base, int32 [M'][2]) and edge
+ * (h_stencil, uint8 [M']); any pointer may be NULL.  Host only (works before
+ * phi_plan_bind). */
+phi_status phi_dr_rows(phi_plan plan, int64_t* h_cells, int32_t* h_base, uint8_t* h_stencil);
 
 const char* phi_status_string(phi_status s);
 

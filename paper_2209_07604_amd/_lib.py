@@ -17,7 +17,7 @@ STATUS = {
 }
 G_PREC = {"c64": 0, "f16": 1, "bf16": 2, "kb": 3}
 HOST_C128, HOST_C64 = 0, 1
-PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH = 1, 2, 4, 8
+PER_CHANNEL, GRAPH, PERSISTENT, FUSED_GH, DR = 1, 2, 4, 8, 16
 
 # every symbol include/phi.h declares
 EXPORTS = [
@@ -25,7 +25,7 @@ EXPORTS = [
     "phi_plan_load_g", "phi_plan_set_theta", "phi_plan_get_info", "phi_plan_set_flags", "phi_plan_set_tuning", "phi_to_plan_order",
     "phi_from_plan_order", "phi_forward", "phi_adjoint", "l2ball_dual_step",
     "phi_plan_check", "phi_plan_set_timing", "phi_plan_get_timing", "phi_plan_autotune",
-    "phi_status_string", "phi_dr_create", "phi_dr_size", "phi_dr_copy", "phi_dr_destroy",
+    "phi_status_string", "phi_dr_setup", "l2ball_dual_step_dr", "phi_dr_plan", "phi_dr_rows",
     "phi_psf", "phi_residual_image", "phi_power_iteration", "phi_plan_load_kb",
     "phi_pdfb_primal", "phi_eps_update", "phi_pdfb_run", "phi_plan_build_g", "phi_plan_read_g",
 ]
@@ -59,6 +59,8 @@ class Info(ctypes.Structure):
         ("ky", ctypes.c_int32), ("kx", ctypes.c_int32), ("tile", ctypes.c_int32),
         ("n_stages", ctypes.c_int32), ("persist_blocks", ctypes.c_int32),
         ("fused", ctypes.c_int32), ("pitch_classes", ctypes.c_int32),
+        ("dr_rows", ctypes.c_int64), ("dr_taps", ctypes.c_int64), ("dr_bytes", ctypes.c_int64),
+        ("dr_max_window", ctypes.c_int32), ("reduced", ctypes.c_int32),
     ]
 
 
@@ -116,10 +118,10 @@ def load():
         "phi_plan_get_timing": [P, I32, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_char_p),
                                 ctypes.POINTER(I32), ctypes.POINTER(I64)],
         "phi_plan_autotune": [P, V, I32],
-        "phi_dr_create": [I32, I32, I64, V, V, V, I32, D, V, ctypes.POINTER(P)],
-        "phi_dr_size": [P, ctypes.POINTER(I64), ctypes.POINTER(I32)],
-        "phi_dr_copy": [P, V, V, V, V, V, V],
-        "phi_dr_destroy": [P],
+        "phi_dr_setup": [P, V, V, V, V],
+        "l2ball_dual_step_dr": [P, V, V, V, V, V, V, V, V, V],
+        "phi_dr_plan": [P, ctypes.POINTER(P)],
+        "phi_dr_rows": [P, V, V, V],
         "phi_plan_build_g": [P, I64, ctypes.POINTER(GBuild), V, V, V, V, V, V],
         "phi_plan_read_g": [P, I64, V, I32, V],
         "phi_pdfb_primal": [P, V, V, V, V, V, V],

@@ -21,6 +21,7 @@
 
 #include "phi.h"
 #include "phi_internal.h"
+#include "phi_plan.h"
 
 using namespace phi;
 
@@ -69,89 +70,11 @@ inline uint16_t f64_to_bf16_rne(double d) {
   return f32_to_bf16_rne((float)r);              // r is representable: exact
 }
 
-struct StageTimer {
-  std::vector<hipEvent_t> pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-  size_t next = 0;
-  double ms[16] = {0};
-  int64_t calls = 0;
-  hipEvent_t get() {
-    if (next == pool.size()) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
-      pool.push_back(e);
-    }
-    return pool[next++];
-  }
-};
-
 const char* kStageNames[] = {"rowfft_fwd", "colfft_fwd", "gather",      "finalize",   "scatter", "merge",
                              "colfft_inv", "rowfft_inv", "pdfb_primal", "eps_update", "dual_gs", "vscale"};
 constexpr int kNumStages = 12;
 
 }  // namespace
-
-// The work lists of one tile edge T (G items, block ranges, merge lists).
-struct WorkList {
-  int T = 32, halo = 1, max_pitch = 0;
-  int64_t partial_elems = 0;
-  std::vector<Item> items;
-  std::vector<BlockInfo> binfo;
-  std::vector<int32_t> tile_ptr;
-  std::vector<TileEntry> entries;
-  std::vector<int32_t> chan_item0;          // [L + 1]
-  // the items again, by pitch (largest first), for launches whose LDS is
-  // sized per pitch; runs of equal pitch as (pitch, first, end)
-  std::vector<Item> items_by_pitch;
-  std::vector<std::array<int32_t, 3>> pitch_runs;
-};
-
-struct phi_plan_s {
-  // geometry
-  int L = 0, Ny = 0, Nx = 0, Ky = 0, Kx = 0, nblk = 0;
-  int gprec = 0, flags = 0, persist = 0;
-  int64_t M = 0, ntaps = 0;
-  std::vector<int32_t> n_blocks, blk_chan, chan_blk0;
-  std::vector<int64_t> blk_u0, blk_n;       // user order start / count per block
-  std::vector<double> theta, sy, sx;
-  // plan order
-  std::vector<int32_t> perm;                // plan -> user (global)
-  std::vector<uint32_t> meta;
-  std::vector<int64_t> tap_off;             // [M + 1]
-  std::vector<uint8_t> S_plan;
-  int smax = 1;
-  // work lists: one per candidate tile edge, `cur` is in use on the device
-  std::vector<WorkList> cands;
-  int cur = 0;
-  WorkList& W() { return cands[cur]; }
-  const WorkList& W() const { return cands[cur]; }
-  // workspace layout
-  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_items_p = 0, off_binfo = 0,
-         off_tptr = 0, off_ent = 0,
-         off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
-         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0;
-  char* ws = nullptr;
-  bool bound = false;
-  std::vector<char> g_loaded;
-  hipStream_t cap_stream = nullptr;
-  // graph cache for the dual step
-  hipGraphExec_t gexec = nullptr;
-  const void* gkey[9] = {nullptr};
-  // timing
-  bool timing = false;
-  StageTimer timer;
-  std::mutex mu;
-
-  // G store bytes per tap (none in the Kaiser-Bessel mode, where taps are
-  // evaluated in the kernels from per-visibility fractional coordinates)
-  size_t g_elem_bytes() const { return gprec == PHI_G_KB ? 0 : gprec == PHI_G_C64 ? 8 : 4; }
-  // the dual step reads each G tap once (gather and G^H in one pass)
-  bool fused() const;
-  int kb_J = 0;                 // window width of the Kaiser-Bessel mode
-  double kb_beta = 0.0, kb_inv_i0b = 0.0;
-  template <typename T_>
-  T_* at(size_t off) const { return reinterpret_cast<T_*>(ws + off); }
-};
 
 // ------------------------------------------------------------------ checks
 static phi_status validate(const phi_desc* d) {
@@ -161,7 +84,8 @@ static phi_status validate(const phi_desc* d) {
   if (d->ny > 4096 || d->nx > 4096) return PHI_ERR_UNSUPPORTED;
   if (!fft_length_supported(2 * d->ny) || !fft_length_supported(2 * d->nx)) return PHI_ERR_UNSUPPORTED;
   if (d->g_prec < PHI_G_C64 || d->g_prec > PHI_G_KB) return PHI_ERR_ARG;
-  if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH)) return PHI_ERR_ARG;
+  if (d->flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH | PHI_DR)) return PHI_ERR_ARG;
+  if ((d->flags & PHI_DR) && d->g_prec == PHI_G_KB) return PHI_ERR_ARG;
   if (d->persist_blocks < 0) return PHI_ERR_ARG;
   const int T = d->tile ? d->tile : 32;
   if (T != 16 && T != 32 && T != 64) return PHI_ERR_ARG;
@@ -373,8 +297,10 @@ bool phi_plan_s::fused() const {
   return gprec != PHI_G_KB && (flags & PHI_FUSED_GH) && fused_lds_bytes(W().max_pitch) > 0;
 }
 
-static void layout(phi_plan_s* p) {
-  size_t o = 0;
+// Workspace regions of a plan from byte offset `base`; with `share`, the
+// grid, half grid, twiddles and Z scales are that plan's (a reduced plan).
+static void layout(phi_plan_s* p, size_t base = 0, const phi_plan_s* share = nullptr) {
+  size_t o = align_up(base);
   auto take = [&](size_t bytes) {
     const size_t r = o;
     o = align_up(o + std::max<size_t>(bytes, 1));
@@ -405,13 +331,23 @@ static void layout(phi_plan_s* p) {
   p->off_scale = take((size_t)p->nblk * 8);
   p->off_bpart = take((size_t)p->nblk * kFinChunks * 16);  // per-block chunk sums of the item norms
   p->off_flag = take(16);
-  p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
-  p->off_half = take((size_t)p->L * p->Ny * p->Kx * 8);
-  p->off_twx = take((size_t)p->Kx * 8);
-  p->off_twy = take((size_t)p->Ky * 8);
-  p->off_sy = take((size_t)p->Ny * 4);
-  p->off_sx = take((size_t)p->Nx * 4);
+  if (share) {
+    p->off_grid = share->off_grid;
+    p->off_half = share->off_half;
+    p->off_twx = share->off_twx;
+    p->off_twy = share->off_twy;
+    p->off_sy = share->off_sy;
+    p->off_sx = share->off_sx;
+  } else {
+    p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
+    p->off_half = take((size_t)p->L * p->Ny * p->Kx * 8);
+    p->off_twx = take((size_t)p->Kx * 8);
+    p->off_twy = take((size_t)p->Ky * 8);
+    p->off_sy = take((size_t)p->Ny * 4);
+    p->off_sx = take((size_t)p->Nx * 4);
+  }
   p->ws_bytes = o;
+  p->ws_total = o;
 }
 
 static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
@@ -427,6 +363,14 @@ static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
   up(p->off_ent, w.entries.data(), w.entries.size() * sizeof(TileEntry));
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e;
+}
+
+static void destroy_impl(phi_plan_s* p) {
+  if (p->dr) destroy_impl(p->dr);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+  for (hipEvent_t e : p->timer.pool) (void)hipEventDestroy(e);
+  delete p;
 }
 
 // ------------------------------------------------------------------ ABI
@@ -552,22 +496,38 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
   p->g_loaded.assign(p->nblk, 0);
   for (int b = 0; b < p->nblk; ++b)
     if (p->blk_n[b] == 0) p->g_loaded[b] = 1;
+  if (d->flags & PHI_DR) {
+    const phi_status sd = dr_build(p, d);
+    if (sd != PHI_OK) {
+      destroy_impl(p);
+      return sd;
+    }
+    // the reduced plan after this plan's regions, then the set-up tables
+    layout(p->dr, p->ws_bytes, p);
+    size_t o = align_up(p->dr->ws_bytes);
+    p->off_drrow = o;
+    o = align_up(o + std::max<size_t>(1, p->drt.rows.size() * sizeof(DrRow)));
+    p->off_drgrp = o;
+    o = align_up(o + std::max<size_t>(1, p->drt.groups.size() * sizeof(DrGroup)));
+    p->off_drcand = o;
+    o = align_up(o + std::max<size_t>(1, p->drt.cands.size() * sizeof(DrCand)));
+    p->ws_total = o;
+  }
   *out = p;
   return PHI_OK;
 }
 
 phi_status phi_plan_destroy(phi_plan p) {
   if (!p) return PHI_ERR_ARG;
-  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
-  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-  for (hipEvent_t e : p->timer.pool) (void)hipEventDestroy(e);
-  delete p;
+  if (p->dr_parent) return PHI_ERR_STATE;  // a reduced plan goes with its plan
+  destroy_impl(p);
   return PHI_OK;
 }
 
 phi_status phi_plan_workspace_size(phi_plan p, size_t* bytes) {
   if (!p || !bytes) return PHI_ERR_ARG;
-  *bytes = p->ws_bytes;
+  if (p->dr_parent) return PHI_ERR_STATE;
+  *bytes = p->ws_total;
   return PHI_OK;
 }
 
@@ -600,6 +560,11 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->persist_blocks = (p->flags & PHI_PERSISTENT) ? p->persist : 0;
   info->fused = p->fused() ? 1 : 0;
   info->pitch_classes = (int32_t)p->W().pitch_runs.size();
+  info->dr_rows = p->dr ? p->dr->M : 0;
+  info->dr_taps = p->dr ? p->dr->ntaps : 0;
+  info->dr_bytes = p->dr ? (int64_t)(p->dr->ntaps * p->dr->g_elem_bytes()) : 0;
+  info->dr_max_window = p->dr ? p->dr->smax : 0;
+  info->reduced = p->dr_parent ? 1 : 0;
   return PHI_OK;
 }
 
@@ -608,11 +573,40 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
     if ((x) != hipSuccess) return PHI_ERR_HIP; \
   } while (0)
 
+static phi_status bind_impl(phi_plan_s* p, void* d_ws, hipStream_t s);
+
 phi_status phi_plan_bind(phi_plan p, void* d_ws, size_t bytes, void* stream) {
   if (!p || !d_ws) return PHI_ERR_ARG;
-  if (bytes < p->ws_bytes || ((uintptr_t)d_ws % kAlign)) return PHI_ERR_WORKSPACE;
-  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->dr_parent) return PHI_ERR_STATE;  // bound with its plan
+  if (bytes < p->ws_total || ((uintptr_t)d_ws % kAlign)) return PHI_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
+  phi_status st;
+  {
+    std::lock_guard<std::mutex> lk(p->mu);
+    st = bind_impl(p, d_ws, s);
+  }
+  if (st != PHI_OK || !p->dr) return st;
+  {
+    std::lock_guard<std::mutex> lk(p->dr->mu);
+    st = bind_impl(p->dr, d_ws, s);
+  }
+  if (st != PHI_OK) return st;
+  std::lock_guard<std::mutex> lk(p->mu);
+  const DrTables& t = p->drt;
+  if (!t.rows.empty())
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_drrow, t.rows.data(), t.rows.size() * sizeof(DrRow),
+                           hipMemcpyHostToDevice, s));
+  if (!t.groups.empty())
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_drgrp, t.groups.data(), t.groups.size() * sizeof(DrGroup),
+                           hipMemcpyHostToDevice, s));
+  if (!t.cands.empty())
+    HIP_TRY(hipMemcpyAsync(p->ws + p->off_drcand, t.cands.data(), t.cands.size() * sizeof(DrCand),
+                           hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return PHI_OK;
+}
+
+static phi_status bind_impl(phi_plan_s* p, void* d_ws, hipStream_t s) {
   p->ws = (char*)d_ws;
   if (p->gexec) {
     (void)hipGraphExecDestroy(p->gexec);
@@ -658,6 +652,10 @@ phi_status phi_plan_set_theta(phi_plan p, const double* h_theta, void* stream) {
   if (!p || !h_theta) return PHI_ERR_ARG;
   for (int b = 0; b < p->nblk; ++b)
     if (!(h_theta[b] > 0.0) || !std::isfinite(h_theta[b])) return PHI_ERR_RANGE;
+  if (p->dr) {  // the reduced plan whitens its blocks with the same theta
+    const phi_status st = phi_plan_set_theta(p->dr, h_theta, stream);
+    if (st != PHI_OK) return st;
+  }
   p->theta.assign(h_theta, h_theta + p->nblk);
   if (!p->bound) return PHI_OK;
   std::vector<float> th(p->nblk);
@@ -671,7 +669,7 @@ phi_status phi_plan_set_theta(phi_plan p, const double* h_theta, void* stream) {
 phi_status phi_plan_load_kb(phi_plan p, int64_t block, const double* h_kappa, void* stream) {
   if (!p) return PHI_ERR_ARG;
   if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
-  if (p->gprec != PHI_G_KB || !p->bound) return PHI_ERR_STATE;
+  if (p->gprec != PHI_G_KB || !p->bound || p->dr_parent) return PHI_ERR_STATE;
   const int64_t u0 = p->blk_u0[block], n = p->blk_n[block];
   if (n == 0) {
     p->g_loaded[block] = 1;
@@ -720,7 +718,7 @@ phi_status phi_plan_load_kb(phi_plan p, int64_t block, const double* h_kappa, vo
 phi_status phi_plan_load_g(phi_plan p, int64_t block, const void* h_windows, int32_t host_type, void* stream) {
   if (!p) return PHI_ERR_ARG;
   if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
-  if (p->gprec == PHI_G_KB) return PHI_ERR_STATE;
+  if (p->gprec == PHI_G_KB || p->dr_parent) return PHI_ERR_STATE;  // reduced rows come from phi_dr_setup
   if (!h_windows && p->blk_n[block] > 0) return PHI_ERR_ARG;
   if (host_type != PHI_HOST_C128 && host_type != PHI_HOST_C64) return PHI_ERR_ARG;
   if (!p->bound) return PHI_ERR_STATE;
@@ -1081,9 +1079,9 @@ phi_status phi_plan_check(phi_plan p, void* stream) {
 
 phi_status phi_plan_set_flags(phi_plan p, int32_t flags) {
   if (!p) return PHI_ERR_ARG;
-  if (flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH)) return PHI_ERR_ARG;
+  if (flags & ~(PHI_PER_CHANNEL | PHI_GRAPH | PHI_PERSISTENT | PHI_FUSED_GH | PHI_DR)) return PHI_ERR_ARG;
   std::lock_guard<std::mutex> lk(p->mu);
-  p->flags = flags;
+  p->flags = (flags & ~PHI_DR) | (p->flags & PHI_DR);  // PHI_DR is fixed at creation
   if (p->gexec) {
     (void)hipGraphExecDestroy(p->gexec);
     p->gexec = nullptr;
@@ -1408,7 +1406,7 @@ phi_status phi_plan_build_g(phi_plan p, int64_t block, const phi_gbuild* desc, c
                             void* stream) {
   if (!p || !desc) return PHI_ERR_ARG;
   if (block < 0 || block >= p->nblk) return PHI_ERR_RANGE;
-  if (p->gprec == PHI_G_KB) return PHI_ERR_STATE;
+  if (p->gprec == PHI_G_KB || p->dr_parent) return PHI_ERR_STATE;
   if (desc->J < 3 || desc->J > 11 || (desc->J & 1) == 0) return PHI_ERR_RANGE;
   if ((d_ant == nullptr) != (d_dde == nullptr)) return PHI_ERR_ARG;
   if (d_ant && (desc->n_ant < 1 || desc->sa < 1 || desc->sa > 7 || (desc->sa & 1) == 0)) return PHI_ERR_RANGE;

@@ -130,6 +130,39 @@ struct BuildArgs {
 };
 hipError_t launch_build_g(const BuildArgs& a, int it0, int it1, hipStream_t s);
 
+// Visibility-gridding reduction (Section 3.4, eqs. 4-5) computed on the
+// device from the plan's stored G.  A reduced row is one gridded cell p of a
+// block's support; it is stored like a row of G: an s x s window (its
+// origin and s in the reduced plan's metadata word) that bounds every cell q
+// with H_pq possibly nonzero.
+struct DrRow {       // one reduced row, in set-up order (block, cell tile, cell)
+  uint32_t cell;     // p_y | p_x << 13
+  int32_t pos;       // its position in the reduced plan's order
+  int64_t tap;       // its first tap in the reduced plan's G store
+};
+struct DrGroup {     // the rows of one block in one T x T tile of cells
+  int32_t row0, row1;
+  int32_t cand0, cand1;  // candidate visibility ranges [cand0, cand1)
+};
+struct DrCand {      // a plan-order range of the block's visibilities whose
+  int32_t v0, v1;    // window origins lie in a tile that can reach the group
+  int64_t tap0;      // first G tap of visibility v0
+};
+struct DrArgs {
+  const uint32_t* meta;     // plan's metadata (plan order)
+  const void* G;            // plan's stored G
+  const uint32_t* rmeta;    // reduced plan's metadata
+  void* H;                  // reduced plan's G store (rows Lam0 H0, rounded once)
+  int gprec;                // 0 c64, 1 f16, 2 bf16 (both stores)
+  const DrRow* rows;
+  const DrGroup* groups;
+  const DrCand* cands;
+  const float2* y;          // whitened data, plan order (may be null: y' = 0)
+  float2* yred;             // y' in the reduced plan's order
+  int Ky, Kx;
+};
+hipError_t launch_dr_setup(const DrArgs& a, int n_groups, hipStream_t s);
+
 // Zero taps kept behind G: a window's fetch reads 64 * NK taps (NK <= 7)
 // from its first tap, past the window's end.
 constexpr int kGPadTaps = 7 * 64;

@@ -16,7 +16,6 @@
 // per tile partial and merged in a fixed order, so results are bitwise
 // reproducible run to run.
 #include <hip/hip_fp16.h>
-#include <cstdlib>
 #include <hip/hip_runtime.h>
 
 #include "phi_internal.h"
@@ -384,11 +383,11 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
 // with conjugate twiddles.
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__ half, float2* __restrict__ grid,
-                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0, int pb,
-                                                      int np) {
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
-  const int n1 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
+  const int np = Kx / W;
+  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
   const float2* in = half + (size_t)l * Ny * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
@@ -406,10 +405,11 @@ __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__
 
 template <int N1, int N2, int W, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, const float2* __restrict__ tw, int Kx,
-                                                  int l0, int pb, int np) {
+                                                  int l0) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N1 * W];
-  const int k2 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
+  const int np = Kx / W;
+  const int k2 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
   float2* g = grid + (size_t)l * N * Kx + (size_t)k2 * Kx;
   for (int e = threadIdx.x; e < N1 * W; e += NT) {
     const int j = e / W, c = e % W;
@@ -431,11 +431,11 @@ __global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, con
 
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__ grid, float2* __restrict__ half,
-                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0, int pb,
-                                                      int np) {
+                                                      const float2* __restrict__ tw, int Ny, int Kx, int l0) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
-  const int n1 = blockIdx.x / np, c0 = (pb + xcd_remap(blockIdx.x % np, np)) * W, l = l0 + blockIdx.y;
+  const int np = Kx / W;
+  const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
   const float2* in = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int k2 = e / W, c = e % W;
@@ -1884,6 +1884,116 @@ __global__ __launch_bounds__(64) void k_build_g(BuildArgs a, int it0) {
   }
 }
 
+// ------------------------------------------------- gridding reduction (DR)
+// Section 3.4, eqs. 4-5, for one block with whitening theta: H = G^H theta^2 G,
+// Lam = H_pp^(-1/2) on the support, y' = Lam G^H theta y, Phi' = Lam H F Z.
+// With H0 = G^H G and Lam0 = H0_pp^(-1/2) this is Lam H = theta Lam0 H0 and
+// y' = Lam0 G^H y: the reduced rows store Lam0 H0 (theta-free, so FP16
+// keeps its range) and the reduced plan applies theta_b like any plan.
+//
+// One wave per reduced row p: it scans the block's visibilities whose window
+// origins lie in the tiles that can reach p (64 at a time, coverage tested
+// per lane), and for each window m covering p, in plan order, adds
+// conj(g_m[p]) g_m[q] to every entry q of the row's window and
+// conj(g_m[p]) y_m to y', in FP64.  Lanes own fixed window entries, so the
+// order of every sum is fixed.  The row is then scaled by Lam0 and rounded
+// once to the stored precision.
+constexpr int kDrMaxSteps = 7;  // row windows up to 21 x 21 = 441 entries
+
+__device__ __forceinline__ double2 load_tap_d(const void* G, int gprec, int64_t t) {
+  if (gprec == 0) {
+    const float2 g = reinterpret_cast<const float2*>(G)[t];
+    return make_double2(g.x, g.y);
+  }
+  const uint32_t r = reinterpret_cast<const uint32_t*>(G)[t];
+  if (gprec == 1)
+    return make_double2((double)(float)__builtin_bit_cast(_Float16, (uint16_t)(r & 0xFFFFu)),
+                        (double)(float)__builtin_bit_cast(_Float16, (uint16_t)(r >> 16)));
+  return make_double2((double)__uint_as_float(r << 16), (double)__uint_as_float(r & 0xFFFF0000u));
+}
+
+__global__ __launch_bounds__(256) void k_dr_setup(DrArgs a) {
+  const DrGroup grp = a.groups[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int r = grp.row0 + wv; r < grp.row1; r += 4) {
+    const DrRow row = a.rows[r];
+    const int py = (int)(row.cell & 8191u), px = (int)((row.cell >> 13) & 8191u);
+    const uint32_t rm = a.rmeta[row.pos];
+    const int s = 2 * (int)(rm >> 26) + 1, oy = (int)(rm & 8191u), ox = (int)((rm >> 13) & 8191u);
+    int dy0 = py - oy, dx0 = px - ox;  // p inside the row's window
+    if (dy0 < 0) dy0 += a.Ky;
+    if (dx0 < 0) dx0 += a.Kx;
+    const float rs = 1.0f / (float)s;
+    double ar[kDrMaxSteps], ai[kDrMaxSteps];
+    int ei[kDrMaxSteps], ej[kDrMaxSteps];
+#pragma unroll
+    for (int k = 0; k < kDrMaxSteps; ++k) {
+      ar[k] = ai[k] = 0.0;
+      const int e = k * 64 + lane;
+      ei[k] = tap_row(e, rs);
+      ej[k] = e - ei[k] * s;
+    }
+    double yr = 0.0, yi = 0.0;
+    for (int c = grp.cand0; c < grp.cand1; ++c) {
+      const DrCand cd = a.cands[c];
+      int64_t tbase = cd.tap0;
+      for (int v = cd.v0; v < cd.v1; v += 64) {
+        const int m = v + lane;
+        const bool live = m < cd.v1;
+        const uint32_t mm = live ? a.meta[m] : 0u;
+        const int S = live ? 2 * (int)(mm >> 26) + 1 : 0;
+        // tap offsets of the 64 windows: exclusive prefix sum of S^2
+        int incl = S * S;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int t = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += t;
+        }
+        const int64_t tm = tbase + (incl - S * S);
+        tbase += __shfl(incl, 63, 64);
+        int ry = py - (int)(mm & 8191u), rx = px - (int)((mm >> 13) & 8191u);
+        if (ry < 0) ry += a.Ky;
+        if (rx < 0) rx += a.Kx;
+        uint64_t cov = __ballot(live && ry < S && rx < S);
+        while (cov) {
+          const int i = __builtin_ctzll(cov);
+          cov &= cov - 1;
+          const int Si = __shfl(S, i, 64), ryi = __shfl(ry, i, 64), rxi = __shfl(rx, i, 64);
+          const int64_t ti = uniform64(__shfl(tm, i, 64));
+          const double2 gp = load_tap_d(a.G, a.gprec, ti + ryi * Si + rxi);  // g_m[p]
+          if (a.y) {
+            const float2 ym = a.y[v + i];
+            yr += gp.x * ym.x + gp.y * ym.y;  // conj(g_m[p]) y_m
+            yi += gp.x * ym.y - gp.y * ym.x;
+          }
+#pragma unroll
+          for (int k = 0; k < kDrMaxSteps; ++k) {
+            const int ty = ryi - dy0 + ei[k], tx = rxi - dx0 + ej[k];
+            if (k * 64 + lane < s * s && ty >= 0 && ty < Si && tx >= 0 && tx < Si) {
+              const double2 g = load_tap_d(a.G, a.gprec, ti + ty * Si + tx);
+              ar[k] += gp.x * g.x + gp.y * g.y;  // conj(g_m[p]) g_m[q]
+              ai[k] += gp.x * g.y - gp.y * g.x;
+            }
+          }
+        }
+      }
+    }
+    // H0_pp sits at entry dy0 * s + dx0; Lam0 = H0_pp^(-1/2) (0 off the support)
+    const int ed = dy0 * s + dx0;
+    double hd = 0.0;
+#pragma unroll
+    for (int k = 0; k < kDrMaxSteps; ++k)
+      if (k == (ed >> 6)) hd = __shfl(ar[k], ed & 63, 64);
+    const double lam = hd > 0.0 ? 1.0 / sqrt(hd) : 0.0;
+#pragma unroll
+    for (int k = 0; k < kDrMaxSteps; ++k) {
+      const int e = k * 64 + lane;
+      if (e < s * s) store_tap(a.H, a.gprec, row.tap + e, lam * ar[k], lam * ai[k]);
+    }
+    if (lane == 0) a.yred[row.pos] = make_float2((float)(lam * yr), (float)(lam * yi));
+  }
+}
+
 // v+ = sigma_b scale_b c over each block's visibilities (fused dual step; a
 // block is one plan-order range): gridDim.x work-groups per block stream it
 __global__ __launch_bounds__(256) void k_vscale(const BlockInfo* __restrict__ blocks, float2* __restrict__ vis,
@@ -1941,40 +2051,11 @@ constexpr int col_split1() {
 // panels in the second pass measured slower).
 constexpr int kColW2 = 32;
 
-// Column slabs of the two-pass transform: with slabs, both passes run on one
-// slab of columns of one channel before the next slab starts, so the second
-// pass reads what the first wrote while it is still in the memory-side cache
-// (256 MB on MI355X; a slab of 2048 columns of an 8192-row grid is 134 MB).
-// Environment PHI_COL_SLAB (columns, a multiple of 256; 0 = whole grid),
-// read once.
-static int col_slab_cols() {
-  static const int v = [] {
-    const char* e = std::getenv("PHI_COL_SLAB");
-    return e ? std::atoi(e) : 0;
-  }();
-  return v;
-}
-
 template <int N1, int N2, bool INV>
-hipError_t colfft2_pass_b(float2* grid, const float2* tw, int Kx, int l0, int nl, int pb, int np, hipStream_t s) {
+hipError_t colfft2_pass_b(float2* grid, const float2* tw, int Kx, int l0, int nl, hipStream_t s) {
   constexpr int W = kColW2, T = panel_threads<N1 * W>();
-  hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, T, INV>), dim3(N2 * np, nl), dim3(T), 0, s, grid, tw, Kx, l0, pb, np);
+  hipLaunchKernelGGL((k_colfft2_b<N1, N2, W, T, INV>), dim3(N2 * (Kx / W), nl), dim3(T), 0, s, grid, tw, Kx, l0);
   return hipGetLastError();
-}
-
-// Panel ranges [pb, pb + np) and channel ranges of the two-pass transform:
-// the whole grid of every channel in one launch per pass, or slab by slab.
-template <typename F>
-static hipError_t colfft2_slabs(int Kx, int W, int l0, int nl, F&& run) {
-  const int np_all = Kx / W, slab = col_slab_cols();
-  const int np_slab = slab > 0 && slab % (8 * W) == 0 && slab < Kx && Kx % slab == 0 ? slab / W : np_all;
-  if (np_slab == np_all) return run(l0, nl, 0, np_all);
-  for (int l = l0; l < l0 + nl; ++l)
-    for (int pb = 0; pb < np_all; pb += np_slab) {
-      const hipError_t e = run(l, 1, pb, np_slab);
-      if (e != hipSuccess) return e;
-    }
-  return hipSuccess;
 }
 
 template <int N>
@@ -1985,13 +2066,9 @@ hipError_t colfft_fwd_n(const float2* half, float2* grid, const float2* tw, int 
     constexpr int N2 = N / N1, W = kColW2;
     if (Kx % W == 0) {
       constexpr int TA = panel_threads<N2 * W>();
-      return colfft2_slabs(Kx, W, l0, nl, [&](int la, int nla, int pb, int np) {
-        hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, TA>), dim3(N1 * np, nla), dim3(TA), 0, s, half, grid, tw, Ny,
-                           Kx, la, pb, np);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        return colfft2_pass_b<N1, N2, false>(grid, tw, Kx, la, nla, pb, np, s);
-      });
+      hipLaunchKernelGGL((k_colfft2_fwd_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, half, grid, tw,
+                         Ny, Kx, l0);
+      return colfft2_pass_b<N1, N2, false>(grid, tw, Kx, l0, nl, s);
     }
   }
   constexpr int W = col_width<N>();
@@ -2011,13 +2088,11 @@ hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int 
       // the pass along k1 runs in place on the grid, which the adjoint no
       // longer needs afterwards
       constexpr int TA = panel_threads<N2 * W>();
-      return colfft2_slabs(Kx, W, l0, nl, [&](int la, int nla, int pb, int np) {
-        const hipError_t e = colfft2_pass_b<N1, N2, true>(const_cast<float2*>(grid), tw, Kx, la, nla, pb, np, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, TA>), dim3(N1 * np, nla), dim3(TA), 0, s, grid, half, tw, Ny,
-                           Kx, la, pb, np);
-        return hipGetLastError();
-      });
+      const hipError_t e = colfft2_pass_b<N1, N2, true>(const_cast<float2*>(grid), tw, Kx, l0, nl, s);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((k_colfft2_inv_a<N1, N2, W, TA>), dim3(N1 * (Kx / W), nl), dim3(TA), 0, s, grid, half, tw,
+                         Ny, Kx, l0);
+      return hipGetLastError();
     }
   }
   constexpr int W = col_width<N>();
@@ -2300,6 +2375,12 @@ hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sig
   if (nb <= 0) return hipSuccess;
   const int chunks = std::max(64, (4096 + nb - 1) / nb);  // >= 4096 work-groups over the chip
   hipLaunchKernelGGL(k_vscale, dim3(chunks, nb), dim3(256), 0, s, blocks, vis, sigma, scale, b0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dr_setup(const DrArgs& a, int n_groups, hipStream_t s) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dr_setup, dim3(n_groups), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -331,7 +331,67 @@ class Plan:
         import torch
         return self._lib.phi_plan_autotune(self._h, _stream(torch, self.device), int(reps))
 
+    # ------------------------------------------- gridding reduction (PHI_DR)
+    def dr_rows(self):
+        """(cells [M'] int64, window origins [M', 2] int32, edges [M'] uint8) of
+        the reduced rows, in reduced order (host, available before binding)."""
+        m = int(self.info()["dr_rows"])
+        cells = np.empty(m, np.int64)
+        base = np.empty((m, 2), np.int32)
+        sten = np.empty(m, np.uint8)
+        L.check(self._lib.phi_dr_rows(self._h, _ptr(cells), _ptr(base), _ptr(sten)), "phi_dr_rows")
+        return cells, base, sten
+
+    def dr_setup(self, y=None, out=None):
+        """Device set-up of the reduction from the loaded G: returns (y' complex64
+        [M'] in reduced order, M'_b int64 [sum B]); y in plan order or None."""
+        import torch
+        m = int(self.info()["dr_rows"])
+        yred = torch.empty(m, dtype=torch.complex64, device=self.device) if out is None else out
+        if y is not None:
+            self._check_vis(y)
+        m_red = np.empty(self.nblk, np.int64)
+        L.check(self._lib.phi_dr_setup(self._h, _dptr(y), _dptr(yred), _ptr(m_red), _stream(torch, self.device)),
+                "phi_dr_setup")
+        return yred, m_red
+
+    def dual_step_dr(self, xt, vred, yred, eps_red, sigma=None, grad=None, rho=None, res=None):
+        """l2ball_dual_step_dr: the reduced dual step in place on vred; returns (grad, rho, res)."""
+        import torch
+        self._check_img(xt)
+        dev = self.device
+        m = int(self.info()["dr_rows"])
+        for t in (vred, yred):
+            if t.dtype != torch.complex64 or not t.is_contiguous() or t.numel() != m:
+                raise ValueError("reduced vectors must be contiguous complex64 [M']")
+        grad = torch.empty((self.L, self.ny, self.nx), dtype=torch.float32, device=dev) if grad is None else grad
+        rho = torch.empty(self.nblk, dtype=torch.float64, device=dev) if rho is None else rho
+        res = torch.empty(self.nblk, dtype=torch.float64, device=dev) if res is None else res
+        self._f64(eps_red, self.nblk, "eps_red")
+        L.check(self._lib.l2ball_dual_step_dr(self._h, _dptr(xt), _dptr(vred), _dptr(yred), _dptr(eps_red),
+                                              _dptr(sigma), _dptr(grad), _dptr(rho), _dptr(res),
+                                              _stream(torch, dev)), "l2ball_dual_step_dr")
+        return grad, rho, res
+
+    def reduced(self):
+        """The reduced plan (phi_dr_plan) as a Plan object borrowing this plan's
+        handle: forward is Phi', adjoint Re Phi'^dagger, dual_step the reduced
+        step; it lives as long as this plan."""
+        h = ctypes.c_void_p()
+        L.check(self._lib.phi_dr_plan(self._h, ctypes.byref(h)), "phi_dr_plan")
+        r = Plan.__new__(Plan)
+        r._lib, r._h, r._owner, r.device = self._lib, h, self, self.device
+        r.ny, r.nx, r.L, r.nblk = self.ny, self.nx, self.L, self.nblk
+        r._n_blocks = self._n_blocks
+        r.g_prec = self.g_prec
+        r.M = int(r.info()["n_vis_total"])
+        r.ws = None
+        return r
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:   # a reduced plan goes with its plan
+            self._h = ctypes.c_void_p()
+            return
         if getattr(self, "_h", None) and self._h.value:
             self._lib.phi_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
@@ -341,36 +401,3 @@ class Plan:
             self.close()
         except Exception:
             pass
-
-
-def dr_reduce(ky, kx, base, stencil, windows, theta=1.0, y=None):
-    """Gridding reduction of one block (libphi, host FP64): returns a dict with
-    the reduced rows' bases [M', 2], window sizes [M'], windows (complex128,
-    W*W each), y' [M'], Lam [M'] and cell indices [M'] (sorted)."""
-    lib = L.load()
-    base = np.ascontiguousarray(base, dtype=np.int32).reshape(-1, 2)
-    stencil = np.ascontiguousarray(stencil, dtype=np.uint8)
-    w = np.ascontiguousarray(windows)
-    if w.dtype == np.complex128:
-        kind = L.HOST_C128
-    elif w.dtype == np.complex64:
-        kind = L.HOST_C64
-    else:
-        raise TypeError("windows must be complex128 or complex64")
-    yy = None if y is None else np.ascontiguousarray(y, dtype=np.complex128)
-    h = ctypes.c_void_p()
-    L.check(lib.phi_dr_create(int(ky), int(kx), len(stencil), _ptr(base), _ptr(stencil), _ptr(w), kind,
-                              float(theta), _ptr(yy), ctypes.byref(h)), "phi_dr_create")
-    try:
-        n = ctypes.c_int64()
-        W = ctypes.c_int32()
-        L.check(lib.phi_dr_size(h, ctypes.byref(n), ctypes.byref(W)), "phi_dr_size")
-        m, W = n.value, W.value
-        out = dict(base=np.empty((m, 2), np.int32), S=np.empty(m, np.uint8),
-                   windows=np.empty(m * W * W, np.complex128), y=np.empty(m, np.complex128),
-                   lam=np.empty(m, np.float64), cell=np.empty(m, np.int64), W=W)
-        L.check(lib.phi_dr_copy(h, _ptr(out["base"]), _ptr(out["S"]), _ptr(out["windows"]), _ptr(out["y"]),
-                                _ptr(out["lam"]), _ptr(out["cell"])), "phi_dr_copy")
-    finally:
-        lib.phi_dr_destroy(h)
-    return out
