@@ -310,13 +310,23 @@ def time_extras(p, x, xt, v0, y, eps, steps, warmup, dev):
     return out
 
 
-def time_dr(p, x, xt, y, head, args, dev):
-    """The visibility-gridding reduction (Section 3.4) on plan p (created with
-    PHI_DR): device set-up time, then the reduced dual step (autotuned,
-    hipGraph) against the unreduced step on the same data; both forms' row and
-    byte counts, and the form the bytes rule keeps."""
+def time_dr(make_plan, blocks, device_g, xt, y_user, head, args, dev):
+    """The visibility-gridding reduction (Section 3.4) on a plan created with
+    PHI_DR from the same blocks (its own G kept in complex64, the reduced rows
+    in the headline precision): device set-up time, then the reduced dual
+    step (autotuned, hipGraph) against the unreduced headline step on the same
+    data; both forms' row and byte counts, and the form the bytes rule keeps."""
     import torch
     from paper_2209_07604_amd import GRAPH, PERSISTENT, FUSED_GH
+    p = make_plan()
+    for k, b in enumerate(blocks):
+        if device_g:
+            p.build_g(k, torch.from_numpy(np.ascontiguousarray(b["kappa"])).to(dev),
+                      torch.from_numpy(np.ascontiguousarray(b["h"])).to(dev),
+                      torch.from_numpy(np.ascontiguousarray(b["a"])).to(dev), J=7)
+        else:
+            p.load_g(k, b["windows"])
+    y = p.to_plan(y_user)
     info = p.info()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -353,17 +363,20 @@ def time_dr(p, x, xt, y, head, args, dev):
     rp.set_timing(False)
     stages, calls = rp.get_timing()
     M = int(info["n_vis_total"])
+    g_bytes_head = int(head["g_bytes"])
     out = {"M": M, "M_reduced": mr, "M_over_M_reduced": M / mr, "taps_G": int(info["n_taps"]),
-           "taps_H": int(info["dr_taps"]), "bytes_G": int(info["g_bytes"]), "bytes_H": int(info["dr_bytes"]),
+           "taps_H": int(info["dr_taps"]), "bytes_G": g_bytes_head, "bytes_H": int(info["dr_bytes"]),
            "largest_row_window": int(info["dr_max_window"]), "setup_ms": setup_ms,
            "ms_per_step_reduced": ms, "ms_per_step_unreduced": head["ms_per_step"],
            "visibilities_per_s_reduced": M / (ms * 1e-3), "tile": ri["tile"], "one_pass": bool(ri["fused"]),
            "stage_ms": {k_: v_ / max(calls, 1) for k_, v_ in stages.items() if v_ > 0},
-           "kept": "reduced" if info["dr_bytes"] < info["g_bytes"] else "unreduced",
+           "kept": "reduced" if info["dr_bytes"] < g_bytes_head else "unreduced",
            "rule": "keep the reduced form only if the rows of Lam H hold fewer bytes than G"}
     out["speedup"] = head["ms_per_step"] / ms
     log("[bench] reduced step: %s" % out)
-    del v, v0, grad, yred
+    del v, v0, grad, yred, y, rp
+    p.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -494,8 +507,7 @@ def main():
     hp = None
     for prec in precs:
         tp = time.time()
-        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev,
-                 flags=DR if (args.dr and prec == hprec) else 0)
+        p = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, None, g_prec=prec, device=dev)
         tile0 = p.info()["tile"]
         log("[bench] plan %s created (%.1f s), workspace %.1f GB" % (prec, time.time() - tp, p.workspace_size() / 1e9))
         torch.cuda.synchronize()
@@ -609,7 +621,11 @@ def main():
     info = r["info"]
     hflags = r["graph_flags"]
     hp.set_flags(hflags)
-    line_dr = time_dr(hp, x, xt, hp_y, r, args, dev) if args.dr else None
+    line_dr = None
+    if args.dr:
+        mk = lambda: Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, base, S, s_y, s_x, theta, g_prec=hprec,
+                          device=dev, flags=DR)
+        line_dr = time_dr(mk, blocks, device_g, xt, y_user, r, args, dev)
     line_extra = {}
     if not args.no_extras:
         log("[bench] %s: forward, adjoint and PDFB iterations" % head)

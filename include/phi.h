@@ -104,7 +104,8 @@ enum {
                            work-group's LDS (e.g. 16-cell tiles)            */
   PHI_DR = 16           /* at plan creation only: also build the plan of the
                            visibility-gridding reduction (phi_dr_setup) in
-                           the same workspace; stored G only                */
+                           the same workspace; stored G only, kept in
+                           complex64 (g_prec applies to the reduced rows)    */
 };
 
 typedef struct {
@@ -409,7 +410,10 @@ phi_status phi_pdfb_run(phi_plan plan, float* d_x, float* d_xt, void* d_v, const
  * support cell p, the window of row p of Lam H: the smallest odd square
  * holding every window that covers p (edge s from S to 2 S - 1).  Those rows
  * form the reduced plan: same channels, blocks and theta, M'_b rows per
- * block, stored in the plan's precision.  Creation fails with
+ * block, stored in g_prec.  The plan's own G is then kept in complex64
+ * whatever g_prec says: Lam rescales each row by its windows' taps at p,
+ * which at the support's edge are the windows' smallest taps, and FP16 /
+ * BF16 storage would not keep their relative precision.  Creation fails with
  * PHI_ERR_UNSUPPORTED where a row's window would exceed 21 x 21 (dense
  * coverage with S > 11) or the grid is smaller than 42 cells; with
  * PHI_ERR_ARG for g_prec = PHI_G_KB.  phi_plan_workspace_size then covers

@@ -18,7 +18,9 @@
 // Hermitian, (Lam H)^H = H Lam and Phi'^H v' is the G^H of those rows, so
 // every stage of the ordinary dual step applies to the reduced plan.
 //
-// phi_dr_setup (device): the row values Lam0 H0 and y' (k_dr_setup).
+// phi_dr_setup (device): the row values Lam0 H0 and y' (k_dr_setup), from the
+// plan's G kept in complex64; the rows are rounded once to the requested
+// precision.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -244,7 +246,8 @@ phi_status phi_dr_setup(phi_plan p, const void* d_y, void* d_yred, int64_t* h_m_
   a.G = p->ws + p->off_G;
   a.rmeta = c->at<uint32_t>(c->off_meta);
   a.H = c->ws + c->off_G;
-  a.gprec = p->gprec;
+  a.gprec_g = p->gprec;
+  a.gprec_h = c->gprec;
   a.rows = p->at<DrRow>(p->off_drrow);
   a.groups = p->at<DrGroup>(p->off_drgrp);
   a.cands = p->at<DrCand>(p->off_drcand);

@@ -403,7 +403,12 @@ phi_status phi_plan_create(const phi_desc* d, phi_plan* out) {
   p->Nx = d->nx;
   p->Ky = 2 * d->ny;
   p->Kx = 2 * d->nx;
-  p->gprec = d->g_prec;
+  // a plan that also reduces keeps its own G in complex64 whatever g_prec
+  // asks for the reduced rows: Lam = H_pp^(-1/2) rescales each gridded row
+  // by its window taps at p, and at the support's edge those are the
+  // windows' smallest taps, whose relative precision FP16 / BF16 storage
+  // would not keep
+  p->gprec = (d->flags & PHI_DR) ? (int)PHI_G_C64 : d->g_prec;
 
   p->flags = d->flags;
   p->persist = d->persist_blocks;

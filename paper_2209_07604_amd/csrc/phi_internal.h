@@ -153,7 +153,7 @@ struct DrArgs {
   const void* G;            // plan's stored G
   const uint32_t* rmeta;    // reduced plan's metadata
   void* H;                  // reduced plan's G store (rows Lam0 H0, rounded once)
-  int gprec;                // 0 c64, 1 f16, 2 bf16 (both stores)
+  int gprec_g, gprec_h;     // storage of G and of the rows: 0 c64, 1 f16, 2 bf16
   const DrRow* rows;
   const DrGroup* groups;
   const DrCand* cands;

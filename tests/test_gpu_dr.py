@@ -3,8 +3,9 @@ computed on the device: phi_dr_setup's rows of Lam H and gridded data
 y' = Gamma y, then Phi', its adjoint and the reduced dual step
 (l2ball_dual_step_dr), against the FP64 oracle of the reduction.
 
-Complex64 G: 1e-5.  FP16 G: 1e-5 against the oracle run on the same rounded
-G, 2e-3 against the FP64 G.  Cases: VLA-like tracks with 7 x 7 windows
+Complex64 rows: 1e-5.  FP16 rows: 2e-3 against the FP64 G (a plan that
+reduces keeps G itself in complex64, so the FP16 error is the rows' own
+rounding).  Cases: VLA-like tracks with 7 x 7 windows
 (4096^2-grid shape at small size), w-stencils up to 11 x 11, and 13 x 13 /
 15 x 15 windows whose reduced rows grow up to 21 x 21.
 """
@@ -69,9 +70,8 @@ def test_device_reduction(name, prec, tol):
     yred = red_plan.from_plan(yred_p).cpu().numpy().astype(np.complex128)   # cell order per block
     torch.cuda.synchronize()
     cells, rbase, rS = plan.dr_rows()
-    # oracle reductions: exact G, and G rounded like the plan's store
-    checks = [(None, tol)] + ([(prec, 1e-5)] if prec != "c64" else [])
-    for gq, bound in checks:
+    assert info["g_bytes"] == 8 * info["n_taps"]          # G kept in complex64
+    for gq, bound in [(None, tol)]:
         reds, yo, ops = [], [], []
         for k, blk in enumerate(blocks):
             w = wins[k][0] if gq is None else quantise(wins[k][0], gq)
