@@ -1405,53 +1405,36 @@ __global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__
 // fixed-order sum of the tile partials covering it (its own tile's items and
 // those of the tiles up to `halo` tiles above/left, with wrap).  The partial
 // list is staged in LDS once per tile; reads of a partial row are coalesced.
+constexpr int kMergeList = 256;
 // Factor of an item's partial in the merge: sigma_b * scale_b after the fused
 // dual step (its partials hold G^H theta c), else 1 (exact: fma(1, v, s) = s + v).
 __device__ __forceinline__ float merge_factor(const double* sigma, const double* scale, int blk) {
   return scale ? (float)((sigma ? sigma[blk] : 1.0) * scale[blk]) : 1.f;
 }
 
-// One work-group per strip of kMergeStripCells x T cells (TS = strip / T
-// consecutive tiles of one tile row): the entry lists of the (halo + 1) x
-// (TS + halo) source tiles that can reach the strip are staged in LDS once,
-// then every cell sums the partials covering it in a fixed order (source
-// tile (dy, dx) row-major, then the tile's items in plan order) and the
-// strip's rows are written as contiguous runs.  A wave's row skips the
-// source tiles no partial of the list reaches; within a source tile, an
-// entry that does not cover a lane's cell reads its partial's first cell and
-// adds it with weight 0 (loads first, four at a time).
-constexpr int kMergeStripCells = 128;
-constexpr int kMergeStrip = 2048;     // staged entries
-constexpr int kMergeSrc = 4 * 11;     // source tiles: (halo + 1) (TS + halo), halo <= 3, TS <= 8
-
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
                                                const TileEntry* __restrict__ ent, int Ky, int Kx, int T,
                                                int halo, int l0, const double* __restrict__ sigma,
                                                const double* __restrict__ scale) {
-  __shared__ int64_t s_off[kMergeStrip];
-  __shared__ int32_t s_pitch[kMergeStrip];
-  __shared__ float s_fac[kMergeStrip];
-  __shared__ int s_beg[kMergeSrc], s_pre[kMergeSrc + 1];
-  __shared__ int s_pmax;
+  __shared__ int64_t s_off[kMergeList];
+  __shared__ int32_t s_pitch[kMergeList];
+  __shared__ float s_fac[kMergeList];
+  __shared__ int32_t s_oy[kMergeList], s_ox[kMergeList];
+  __shared__ int s_beg[16], s_pre[17];
   const int l = l0 + blockIdx.y;
   const int nty = Ky / T, ntx = Kx / T;
-  const int TSmax = kMergeStripCells / T;
-  const int nstrip = (ntx + TSmax - 1) / TSmax;
-  const int ty = blockIdx.x / nstrip, tx0 = (blockIdx.x % nstrip) * TSmax;
-  const int TS = min(TSmax, ntx - tx0), W = TS * T;
-  const int hw = halo + 1, sw = TS + halo, nsrc = hw * sw;
+  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  const int hw = halo + 1, nsrc = hw * hw;   // halo <= 3: at most 16 source tiles
   if ((int)threadIdx.x < nsrc) {
-    const int dy = threadIdx.x / sw, j = threadIdx.x % sw;  // source tile (ty - dy, tx0 - halo + j)
-    int sty = ty - dy, stx = tx0 - halo + j;
+    const int dy = threadIdx.x / hw, dx = threadIdx.x % hw;
+    int sty = ty - dy, stx = tx - dx;
     while (sty < 0) sty += nty;
     while (stx < 0) stx += ntx;
-    while (stx >= ntx) stx -= ntx;
     const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
     s_beg[threadIdx.x] = tile_ptr[tile];
     s_pre[threadIdx.x + 1] = tile_ptr[tile + 1] - tile_ptr[tile];
   }
-  if (threadIdx.x == 0) s_pmax = 0;
   __syncthreads();
   if (threadIdx.x == 0) {
     s_pre[0] = 0;
@@ -1459,78 +1442,72 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
   }
   __syncthreads();
   const int n = s_pre[nsrc];
-  const bool staged = n <= kMergeStrip;
-  if (staged) {
-    int pm = 0;
-    for (int e = threadIdx.x; e < n; e += 256) {
-      int j = 0;
-      while (e >= s_pre[j + 1]) ++j;
-      const TileEntry te = ent[s_beg[j] + (e - s_pre[j])];
-      s_off[e] = te.poff;
-      s_pitch[e] = te.pitch;
-      s_fac[e] = merge_factor(sigma, scale, te.blk);
-      pm = max(pm, te.pitch);
-    }
-    if (pm > 0) atomicMax(&s_pmax, pm);
+  for (int e = threadIdx.x; e < n && e < kMergeList; e += 256) {
+    int j = 0;
+    while (e >= s_pre[j + 1]) ++j;
+    const TileEntry te = ent[s_beg[j] + (e - s_pre[j])];
+    s_off[e] = te.poff;
+    s_pitch[e] = te.pitch;
+    s_fac[e] = merge_factor(sigma, scale, te.blk);
+    s_oy[e] = (j / hw) * T;
+    s_ox[e] = (j % hw) * T;
   }
   __syncthreads();
-  const int pmax = staged ? s_pmax : T * hw;
   float2* out = grid + (int64_t)l * Ky * Kx;
-  for (int e = threadIdx.x; e < T * W; e += 256) {
-    const int r = e / W, c = e - (e / W) * W;
-    const int t = c / T, cc = c - t * T;
-    // the rows of a wave lie in one tile row r (W >= 64), so dy skips are uniform
+  for (int e = threadIdx.x; e < T * T; e += 256) {
+    const int r = e / T, c = e % T;
     float sx = 0.f, sy = 0.f;
-    if (n > 0) {
+    if (n <= kMergeList) {
+      // four entries at a time, loads first: an entry that does not cover
+      // this cell reads its partial's first cell and adds it with weight 0
+      // (the sum keeps its order; partial cells are finite)
+      int k = 0;
+      for (; k + 4 <= n; k += 4) {
+        float2 v[4];
+        float f[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ly = r + s_oy[k + u], lx = c + s_ox[k + u], P = s_pitch[k + u];
+          const bool in = ly < P && lx < P;
+          f[u] = in ? s_fac[k + u] : 0.f;
+          v[u] = partials[s_off[k + u] + (in ? (int64_t)ly * P + lx : 0)];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          sx = __builtin_fmaf(f[u], v[u].x, sx);
+          sy = __builtin_fmaf(f[u], v[u].y, sy);
+        }
+      }
+      for (; k < n; ++k) {
+        const int ly = r + s_oy[k], lx = c + s_ox[k], P = s_pitch[k];
+        if (ly < P && lx < P) {
+          const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
+          sx = __builtin_fmaf(s_fac[k], v.x, sx);
+          sy = __builtin_fmaf(s_fac[k], v.y, sy);
+        }
+      }
+    } else {  // long lists: same order, read from global memory
       for (int dy = 0; dy <= halo; ++dy) {
-        const int ly = r + dy * T;
-        if (ly >= pmax) break;
+        int sty = ty - dy;
+        while (sty < 0) sty += nty;
         for (int dx = 0; dx <= halo; ++dx) {
-          const int lx = cc + dx * T;
-          const int j = dy * sw + (t - dx + halo);
-          if (staged) {
-            if (__ballot(lx < pmax) == 0) continue;
-            const int k0 = s_pre[j], k1 = s_pre[j + 1];
-            int k = k0;
-            for (; k + 4 <= k1; k += 4) {
-              float2 v[4];
-              float f[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int P = s_pitch[k + u];
-                const bool in = ly < P && lx < P;
-                f[u] = in ? s_fac[k + u] : 0.f;
-                v[u] = partials[s_off[k + u] + (in ? (int64_t)ly * P + lx : 0)];
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                sx = __builtin_fmaf(f[u], v[u].x, sx);
-                sy = __builtin_fmaf(f[u], v[u].y, sy);
-              }
-            }
-            for (; k < k1; ++k) {
-              const int P = s_pitch[k];
-              if (ly < P && lx < P) {
-                const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
-                sx = __builtin_fmaf(s_fac[k], v.x, sx);
-                sy = __builtin_fmaf(s_fac[k], v.y, sy);
-              }
-            }
-          } else {  // long lists: same order, read from global memory
-            for (int k = s_beg[j]; k < s_beg[j] + (s_pre[j + 1] - s_pre[j]); ++k) {
-              const TileEntry te = ent[k];
-              if (ly < te.pitch && lx < te.pitch) {
-                const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
-                const float f = merge_factor(sigma, scale, te.blk);
-                sx = __builtin_fmaf(f, v.x, sx);
-                sy = __builtin_fmaf(f, v.y, sy);
-              }
+          int stx = tx - dx;
+          while (stx < 0) stx += ntx;
+          const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
+          const int ly = r + dy * T, lx = c + dx * T;
+          for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
+            const TileEntry te = ent[k];
+            if (ly < te.pitch && lx < te.pitch) {
+              const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+              const float f = merge_factor(sigma, scale, te.blk);
+              sx = __builtin_fmaf(f, v.x, sx);
+              sy = __builtin_fmaf(f, v.y, sy);
             }
           }
         }
       }
     }
-    out[(int64_t)(ty * T + r) * Kx + tx0 * T + c] = make_float2(sx, sy);
+    out[(int64_t)(ty * T + r) * Kx + tx * T + c] = make_float2(sx, sy);
   }
 }
 
@@ -2321,10 +2298,8 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
                         int Ky, int Kx, int T, int halo, int l0, int nl, const double* sigma, const double* scale,
                         hipStream_t s) {
-  if (halo > 3 || T > kMergeStripCells) return hipErrorInvalidValue;
-  const int ts = kMergeStripCells / T, ntx = Kx / T;
-  const int strips = (Ky / T) * ((ntx + ts - 1) / ts);
-  hipLaunchKernelGGL(k_merge, dim3(strips, nl), dim3(256), 0, s, grid, partials, tile_ptr, entries, Ky, Kx, T, halo,
+  const int tiles = (Ky / T) * (Kx / T);
+  hipLaunchKernelGGL(k_merge, dim3(tiles, nl), dim3(256), 0, s, grid, partials, tile_ptr, entries, Ky, Kx, T, halo,
                      l0, sigma, scale);
   return hipGetLastError();
 }
