@@ -332,6 +332,16 @@ phi_status phi_residual_image(phi_plan plan, const float* d_x, const void* d_y, 
 phi_status phi_power_iteration(phi_plan plan, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu,
                                void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the power
+ * method of phi_power_iteration with its scratch image in a fixed device
+ * array of 32 MiB per GPU (held from library load until the process ends)
+ * instead of d_tmp.  It allocates nothing; the plan must be bound.  Channels
+ * x pixels (L Ny Nx) above 8 Mi (32 MiB of float32) return
+ * PHI_ERR_UNSUPPORTED.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU race (serialise them on one stream). */
+phi_status phi_power_iteration_static(phi_plan plan, float* d_x, int32_t n_iter, double* d_nu, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Regularizer-free primal-dual forward-backward (PDFB) loop: eq. (2) with the
  * regularization reduced to the non-negativity constraint on the image cube

@@ -28,6 +28,7 @@ EXPORTS = [
     "phi_status_string", "phi_dr_setup", "l2ball_dual_step_dr", "phi_dr_plan", "phi_dr_rows",
     "phi_psf", "phi_residual_image", "phi_power_iteration", "phi_plan_load_kb",
     "phi_pdfb_primal", "phi_eps_update", "phi_pdfb_run", "phi_plan_build_g", "phi_plan_read_g",
+    "phi_power_iteration_static",
 ]
 
 
@@ -124,6 +125,7 @@ def load():
         "phi_dr_rows": [P, V, V, V],
         "phi_plan_build_g": [P, I64, ctypes.POINTER(GBuild), V, V, V, V, V, V],
         "phi_plan_read_g": [P, I64, V, I32, V],
+        "phi_power_iteration_static": [P, V, I32, V, V],
         "phi_pdfb_primal": [P, V, V, V, V, V, V],
         "phi_eps_update": [P, V, V, ctypes.POINTER(EpsRule), V, V, V],
         "phi_pdfb_run": [P, V, V, V, V, V, V, V, I32, ctypes.POINTER(EpsRule), V, V, V, V, V, V],

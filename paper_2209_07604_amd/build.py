@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libphi.so")
 SOURCES = [os.path.join(CSRC, "phi_kernels.hip"), os.path.join(CSRC, "phi_host.cpp"),
-           os.path.join(CSRC, "phi_dr.cpp")]
+           os.path.join(CSRC, "phi_dr.cpp"), os.path.join(CSRC, "phi_static.cpp")]
 ARCH = os.environ.get("PHI_OFFLOAD_ARCH", "gfx950")
 
 

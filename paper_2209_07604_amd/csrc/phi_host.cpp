@@ -1292,6 +1292,13 @@ phi_status phi_residual_image(phi_plan p, const float* d_x, const void* d_y, con
 }
 
 phi_status phi_power_iteration(phi_plan p, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu, void* stream) {
+  return power_iteration_impl(p, d_x, d_tmp, n_iter, d_nu, stream);
+}
+
+}  // extern "C"
+
+phi_status power_iteration_impl(phi_plan_s* p, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu,
+                                void* stream) {
   const phi_status st = ready(p);
   if (st != PHI_OK) return st;
   if (!d_x || !d_tmp || !d_nu || d_x == d_tmp) return PHI_ERR_ARG;
@@ -1314,6 +1321,8 @@ phi_status phi_power_iteration(phi_plan p, float* d_x, float* d_tmp, int32_t n_i
   if (a != d_x) HIP_TRY(hipMemcpyAsync(d_x, a, (size_t)p->L * n * sizeof(float), hipMemcpyDeviceToDevice, s));
   return PHI_OK;
 }
+
+extern "C" {
 
 // ------------------------------------------------------------- PDFB loop
 static bool rule_ok(const phi_eps_rule* r) {

@@ -117,3 +117,7 @@ struct phi_plan_s {
 
 // Reduced plan and set-up tables of a plan created with PHI_DR (phi_dr.cpp).
 phi_status dr_build(phi_plan_s* p, const phi_desc* d);
+
+// phi_power_iteration with its scratch image d_tmp given (phi_host.cpp).
+phi_status power_iteration_impl(phi_plan_s* p, float* d_x, float* d_tmp, int32_t n_iter, double* d_nu,
+                                void* stream);

@@ -212,6 +212,16 @@ class Plan:
                                               _stream(torch, self.device)), "phi_power_iteration")
         return nu
 
+    def power_iteration_static(self, x, n_iter):
+        """power_iteration without a scratch image (phi_power_iteration_static:
+        the library's fixed per-GPU scratch array, no allocation)."""
+        import torch
+        self._check_img(x)
+        nu = torch.empty(self.L, dtype=torch.float64, device=self.device)
+        L.check(self._lib.phi_power_iteration_static(self._h, _dptr(x), int(n_iter), _dptr(nu),
+                                                     _stream(torch, self.device)), "phi_power_iteration_static")
+        return nu
+
     # ------------------------------------------------------------- G builder
     def build_g(self, block, kappa, h, a, ant=None, dde=None, J=7):
         """Compute block `block`'s rows of G on the device (phi_plan_build_g).
