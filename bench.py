@@ -225,10 +225,16 @@ def stage_alg_bytes(info, L, N, K):
     pass's bytes except the c read and v+ write, which the v+ scale does."""
     T, M = float(info["n_taps"]), float(info["n_vis_total"])
     G = float(info["g_bytes"])
-    return {"rowfft_fwd": L * (4.0 * N + 4.0 * K), "colfft_fwd": L * 12.0 * K,
-            "gather": G + 28.0 * M + L * 8.0 * K, "scatter": G + 20.0 * M,
-            "dual_gs": 2.0 * G + 32.0 * M + L * 8.0 * K, "vscale": 16.0 * M, "finalize": 0.0,
-            "merge": L * 8.0 * K, "colfft_inv": L * 12.0 * K, "rowfft_inv": L * (4.0 * K + 4.0 * N)}
+    out = {"rowfft_fwd": L * (4.0 * N + 4.0 * K), "colfft_fwd": L * 12.0 * K,
+           "gather": G + 28.0 * M + L * 8.0 * K, "scatter": G + 20.0 * M,
+           "dual_gs": 2.0 * G + 32.0 * M + L * 8.0 * K, "vscale": 16.0 * M, "finalize": 0.0,
+           "merge": L * 8.0 * K, "colfft_inv": L * 12.0 * K, "rowfft_inv": L * (4.0 * K + 4.0 * N)}
+    if info.get("fft_image_first"):
+        # columns of the image first (x in, the Ky x Nx intermediate out: 4 K),
+        # then the rows (intermediate in, grid out); the adjoint mirrors it
+        out.update(colfft_fwd=L * (4.0 * N + 4.0 * K), rowfft_fwd=L * 12.0 * K,
+                   rowfft_inv=L * 12.0 * K, colfft_inv=L * (4.0 * K + 4.0 * N))
+    return out
 
 
 def _event_ms(fn, n):

@@ -160,6 +160,10 @@ typedef struct {
   int64_t dr_bytes;            /* device bytes of the reduced rows           */
   int32_t dr_max_window;       /* largest reduced-row window edge s          */
   int32_t reduced;             /* 1 on the handle phi_dr_plan returns        */
+  int32_t fft_image_first;     /* 1 if the 2-D DFT runs columns first, on the
+                                  image (grids of 3072 ... 8192 rows with
+                                  Nx / 2 a multiple of 8), else rows first   */
+  int32_t reserved;
 } phi_info;
 
 /* Validate `desc`, sort visibilities and build the work lists (host only,

@@ -62,6 +62,7 @@ class Info(ctypes.Structure):
         ("fused", ctypes.c_int32), ("pitch_classes", ctypes.c_int32),
         ("dr_rows", ctypes.c_int64), ("dr_taps", ctypes.c_int64), ("dr_bytes", ctypes.c_int64),
         ("dr_max_window", ctypes.c_int32), ("reduced", ctypes.c_int32),
+        ("fft_image_first", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -570,6 +570,7 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->dr_bytes = p->dr ? (int64_t)(p->dr->ntaps * p->dr->g_elem_bytes()) : 0;
   info->dr_max_window = p->dr ? p->dr->smax : 0;
   info->reduced = p->dr_parent ? 1 : 0;
+  info->fft_image_first = fft_image_first(p->Ky, p->Nx) ? 1 : 0;
   return PHI_OK;
 }
 
@@ -876,6 +877,20 @@ struct Runner {
   // channel range [l0, l1), matching block and item ranges
   void fwd_fft(const float* x, int l0, int l1) {
     const int nl = l1 - l0;
+    if (fft_image_first(p->Ky, p->Nx)) {
+      // columns of the image first (packed columns in the grid buffer, T in
+      // the half grid), then the Ky rows of T into the grid
+      stage(1, [&] {
+        return launch_colr_fwd(p->Ky, x, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
+                               p->at<float>(p->off_sy), p->at<float>(p->off_sx), p->at<float2>(p->off_twy), p->Ny,
+                               p->Nx, l0, nl, s);
+      });
+      stage(0, [&] {
+        return launch_rowc_fwd(p->Kx, p->at<float2>(p->off_half), p->at<float2>(p->off_grid),
+                               p->at<float2>(p->off_twx), p->Ky, l0, nl, s);
+      });
+      return;
+    }
     stage(0, [&] {
       return launch_rowfft_fwd(p->Kx, x, p->at<float2>(p->off_half), p->at<float>(p->off_sy),
                                p->at<float>(p->off_sx), p->at<float2>(p->off_twx), p->Ny, p->Nx, l0, nl, s);
@@ -893,6 +908,20 @@ struct Runner {
                           p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, l0, nl, msig, mscale,
                           s);
     });
+    if (fft_image_first(p->Ky, p->Nx)) {
+      // rows first (the Nx kept columns into the half grid), then the image's
+      // columns (packed columns in the grid buffer), real part, Z^T
+      stage(7, [&] {
+        return launch_rowc_inv(p->Kx, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
+                               p->at<float2>(p->off_twx), p->Ky, l0, nl, s);
+      });
+      stage(6, [&] {
+        return launch_colr_inv(p->Ky, p->at<float2>(p->off_half), p->at<float2>(p->off_grid), x,
+                               p->at<float>(p->off_sy), p->at<float>(p->off_sx), p->at<float2>(p->off_twy), p->Ny,
+                               p->Nx, l0, nl, s);
+      });
+      return;
+    }
     stage(6, [&] {
       return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
                                p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);

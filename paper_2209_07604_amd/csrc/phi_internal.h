@@ -83,6 +83,19 @@ hipError_t launch_colfft_inv(int Ky, const float2* grid, float2* half, const flo
                              int Kx, int l0, int nl, hipStream_t s);
 hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* sy, const float* sx,
                              const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
+// Image-first order for grids whose columns take two passes (Ky = 3072 ...
+// 8192, Nx / 2 a multiple of 8): columns of the image first (zp: packed
+// scratch [L][Ky][Nx/2], T: [L][Ky][Nx]), then the Ky rows of T into the
+// grid; the adjoint runs the mirror.
+bool fft_image_first(int Ky, int Nx);
+hipError_t launch_colr_fwd(int Ky, const float* x, float2* zp, float2* T, const float* sy, const float* sx,
+                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
+hipError_t launch_rowc_fwd(int Kx, const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl,
+                           hipStream_t s);
+hipError_t launch_rowc_inv(int Kx, const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl,
+                           hipStream_t s);
+hipError_t launch_colr_inv(int Ky, const float2* T, float2* zp, float* x, const float* sy, const float* sx,
+                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
 
 // mode: 0 forward (write y), 1 residual (c = v/sigma + phi - y into v; norms)
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y,

@@ -451,6 +451,235 @@ __global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__
   }
 }
 
+// --------------------------------------- image-first 2-D transform (Ky = N1 N2)
+// Grids whose columns take two passes (Ky = N1 N2, 3072 ... 8192 points) run
+// the 2-D DFT columns first, on the image itself.  Real columns 2c and 2c+1
+// are packed as one complex column z = s x_2c + i s x_2c+1 (the Z scales
+// applied on load), whose Ky-point DFT Z gives both real columns'
+// transforms: T_2c[k] = (Z[k] + conj Z[-k]) / 2, T_2c+1[k] = (Z[k] -
+// conj Z[-k]) / (2i).  Each of the Ky rows of T (Nx nonzero inputs of Kx)
+// then takes a Kx-point DFT into the grid.  The adjoint mirrors it: rows
+// first, keeping the Nx columns Z^T reads, then columns, of which only the
+// real part is kept: that is the inverse DFT of the Hermitian part
+// (t[k] + conj t[-k]) / 2, and two such real-output transforms are packed
+// as one complex transform.  Per channel and direction this moves
+// 4 N + 4 K (image, packed columns between the column passes: 2 K each
+// way) + 4 K (T) + 12 K (rows) bytes instead of the 28 K + 4 N of rows first.
+//
+// Column pass A (forward): one n1 per work-group, W packed columns; rows
+// n = n1 + N1 n2 of the image (centred wrap), transform along n2, twiddle
+// w_N^(n1 k2), store packed row k2 + N2 n1 of zp [Ky][Nx/2].
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colr_fwd_a(const float* __restrict__ x, float2* __restrict__ zp,
+                                                   const float* __restrict__ sy, const float* __restrict__ sx,
+                                                   const float2* __restrict__ tw, int Ny, int Nx, int l0,
+                                                   size_t zs) {
+  constexpr int N = N1 * N2;
+  __shared__ float2 buf[N2 * W];
+  const int Nh = Nx / 2, npc = Nh / W;
+  const int n1 = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
+  const float* xi = x + (size_t)l * Ny * Nx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+    const int p = (n < N / 2 ? n : n - N) + Ny / 2;
+    float2 v = make_float2(0.f, 0.f);
+    if (p >= 0 && p < Ny) {
+      const int q = 2 * (c0 + c);
+      const float2 xv = *reinterpret_cast<const float2*>(xi + (size_t)p * Nx + q);
+      const float s = sy[p];
+      v = make_float2(s * sx[q] * xv.x, s * sx[q + 1] * xv.y);
+    }
+    buf[e] = v;
+  }
+  __syncthreads();
+  fft_run<N2, W, NT, false, 1, N1>(buf, tw);
+  float2* out = zp + (size_t)l * zs + (size_t)N2 * n1 * Nh;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int k2 = e / W, c = e % W;
+    out[(size_t)k2 * Nh + c0 + c] = cmul(buf[e], tw[n1 * k2]);
+  }
+}
+
+// Entry of k = k2 + N2 k1 that holds Z[-k]: (group, k1) of the pair
+// (k2a, k2b = (N2 - k2a) mod N2) a work-group holds (group 0 is k2a).
+template <int N1, int N2>
+__device__ __forceinline__ int mirror_k1(int k2, int k1) {
+  return k2 == 0 ? (N1 - k1) % N1 : N1 - 1 - k1;
+}
+
+// Column pass B (forward): the pair of k2 groups (k2a, N2 - k2a) per
+// work-group, transform along n1 -> k1 in place, then the split of each
+// packed column into its two real columns' transforms, written as T rows
+// k = k2 + N2 k1 [Ky][Nx].
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp, float2* __restrict__ T,
+                                                   const float2* __restrict__ tw, int Nx, int l0, size_t zs) {
+  constexpr int N = N1 * N2, W2 = 2 * W;
+  __shared__ float2 buf[N1 * W2];  // (k1, col): col < W group a, >= W group b
+  const int Nh = Nx / 2, npc = Nh / W;
+  const int g = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
+  const int k2a = g, k2b = (N2 - g) % N2;
+  const float2* in = zp + (size_t)l * zs;
+  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
+    const int j = e / W2, col = e % W2, c = col % W, k2 = col < W ? k2a : k2b;
+    buf[e] = in[(size_t)(N2 * j + k2) * Nh + c0 + c];
+  }
+  __syncthreads();
+  fft_run<N1, W2, NT, false, 1, N2>(buf, tw);
+  float4* out = reinterpret_cast<float4*>(T + (size_t)l * N * Nx);
+  const bool two = k2b != k2a;
+  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
+    const int k1 = e / W2, col = e % W2, grp = col / W, c = col % W;
+    if (grp == 1 && !two) continue;
+    const int k2 = grp ? k2b : k2a;
+    // Z[-k] lives in the other group (or the same one when self-paired)
+    const int mg = two ? 1 - grp : 0, mk1 = mirror_k1<N1, N2>(k2, k1);
+    const float2 z = buf[e], zm = buf[mk1 * W2 + mg * W + c];
+    // T_2c = (z + conj zm) / 2, T_2c+1 = (z - conj zm) / (2i)
+    const float2 a = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
+    const float2 b = make_float2(0.5f * (z.y + zm.y), 0.5f * (zm.x - z.x));
+    out[((size_t)(k2 + N2 * k1) * Nx) / 2 + c0 + c] = make_float4(a.x, a.y, b.x, b.y);
+  }
+}
+
+// Row pass (forward): row k of T (Nx values, centred in Kx = N cells) to
+// grid row k.  Input cell n is nonzero for n < Nx/2 or n >= N - Nx/2, so
+// with M = N/2 = Nx: X[2k'] = DFT_M(u)[k'], X[2k'+1] = DFT_M(v)[k'] with
+// u[m] = T[(m + Nx/2) mod Nx] and v[m] = +-u[m] w_N^m (minus for m >= Nx/2);
+// u and v run interleaved, so the transformed buffer is the grid row.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rowc_fwd(const float2* __restrict__ T, float2* __restrict__ grid,
+                                                 const float2* __restrict__ tw, int Ky, int l0) {
+  constexpr int M = N / 2, Nx = M;
+  __shared__ float2 buf[N];
+  const int k = blockIdx.x, l = l0 + blockIdx.y;
+  const float2* t = T + ((size_t)l * Ky + k) * Nx;
+  for (int m = threadIdx.x; m < M; m += NT) {
+    const bool lo = m < Nx / 2;
+    const float2 u = t[lo ? m + Nx / 2 : m - Nx / 2];
+    const float2 w = tw[m];
+    const float2 uw = cmul(u, w);
+    buf[2 * m] = u;
+    buf[2 * m + 1] = lo ? uw : make_float2(-uw.x, -uw.y);
+  }
+  __syncthreads();
+  fft_run<M, 2, NT, false, 1, 2>(buf, tw);
+  float4* out = reinterpret_cast<float4*>(grid + ((size_t)l * Ky + k) * N);
+  const float4* b4 = reinterpret_cast<const float4*>(buf);
+  for (int i = threadIdx.x; i < M; i += NT) out[i] = b4[i];
+}
+
+// Row pass (inverse): grid row k to row k of T' (the Nx kept columns):
+// x[n] = E[n mod M] + w_N^-n O[n mod M] with E, O the inverse DFTs of the
+// even and odd samples, run interleaved.
+template <int N, int NT>
+__global__ __launch_bounds__(NT) void k_rowc_inv(const float2* __restrict__ grid, float2* __restrict__ T,
+                                                 const float2* __restrict__ tw, int Ky, int l0) {
+  constexpr int M = N / 2, Nx = M;
+  __shared__ float2 buf[N];
+  const int k = blockIdx.x, l = l0 + blockIdx.y;
+  const float4* in = reinterpret_cast<const float4*>(grid + ((size_t)l * Ky + k) * N);
+  float4* b4 = reinterpret_cast<float4*>(buf);
+  for (int i = threadIdx.x; i < M; i += NT) b4[i] = in[i];
+  __syncthreads();
+  fft_run<M, 2, NT, true, 1, 2>(buf, tw);
+  float2* t = T + ((size_t)l * Ky + k) * Nx;
+  for (int q = threadIdx.x; q < Nx; q += NT) {
+    const bool hi = q >= Nx / 2;
+    const int n = hi ? q - Nx / 2 : q - Nx / 2 + N, m = hi ? q - Nx / 2 : q + Nx / 2;
+    float2 w = tw[n];
+    w.y = -w.y;
+    const float2 o = cmul(buf[2 * m + 1], w), e = buf[2 * m];
+    t[q] = make_float2(e.x + o.x, e.y + o.y);
+  }
+}
+
+// Column pass B (inverse): the pair (k2a, N2 - k2a), the Hermitian parts of
+// the two real columns of each packed column combined as
+// (t2c[k] + conj t2c[-k]) / 2 + i (t2c+1[k] + conj t2c+1[-k]) / 2, inverse
+// transform along k1 -> n1, twiddle conj w_N^(n1 k2), store packed rows
+// k2 + N2 n1 of zp.
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colr_inv_b(const float2* __restrict__ T, float2* __restrict__ zp,
+                                                   const float2* __restrict__ tw, int Nx, int l0, size_t zs) {
+  constexpr int N = N1 * N2, W2 = 2 * W;
+  __shared__ float4 raw[N1 * W2];  // (k1, col): the two real columns' T' values
+  float2* buf = reinterpret_cast<float2*>(raw);  // packed values, (k1, col), after the split
+  const int Nh = Nx / 2, npc = Nh / W;
+  const int g = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
+  const int k2a = g, k2b = (N2 - g) % N2;
+  const bool two = k2b != k2a;
+  const float4* in = reinterpret_cast<const float4*>(T + (size_t)l * N * Nx);
+  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
+    const int j = e / W2, col = e % W2, c = col % W, k2 = col < W ? k2a : k2b;
+    raw[e] = in[((size_t)(k2 + N2 * j) * Nx) / 2 + c0 + c];
+  }
+  __syncthreads();
+  constexpr int PER = (N1 * W2 + NT - 1) / NT;
+  float2 h[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W2) {
+      const int k1 = e / W2, col = e % W2, grp = col / W, c = col % W;
+      const int k2 = grp ? k2b : k2a;
+      const int mg = two ? 1 - grp : 0, mk1 = mirror_k1<N1, N2>(k2, k1);
+      const float4 a = raw[e], b = raw[mk1 * W2 + mg * W + c];
+      // (a.xy + conj b.xy) / 2 + i (a.zw + conj b.zw) / 2
+      h[i] = make_float2(0.5f * (a.x + b.x) - 0.5f * (a.w - b.w), 0.5f * (a.y - b.y) + 0.5f * (a.z + b.z));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W2) buf[e] = h[i];
+  }
+  __syncthreads();
+  fft_run<N1, W2, NT, true, 1, N2>(buf, tw);
+  float2* out = zp + (size_t)l * zs;
+  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
+    const int n1 = e / W2, col = e % W2, grp = col / W, c = col % W;
+    if (grp == 1 && !two) continue;
+    const int k2 = grp ? k2b : k2a;
+    float2 w = tw[n1 * k2];
+    w.y = -w.y;
+    out[(size_t)(k2 + N2 * n1) * Nh + c0 + c] = cmul(buf[e], w);
+  }
+}
+
+// Column pass A (inverse): one n1 per work-group, inverse transform along
+// k2 -> n2, rows n = n1 + N1 n2 kept by Z^T, real and imaginary parts are the
+// two real columns, times the Z scales.
+template <int N1, int N2, int W, int NT>
+__global__ __launch_bounds__(NT) void k_colr_inv_a(const float2* __restrict__ zp, float* __restrict__ x,
+                                                   const float* __restrict__ sy, const float* __restrict__ sx,
+                                                   const float2* __restrict__ tw, int Ny, int Nx, int l0,
+                                                   size_t zs) {
+  constexpr int N = N1 * N2;
+  __shared__ float2 buf[N2 * W];
+  const int Nh = Nx / 2, npc = Nh / W;
+  const int n1 = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
+  const float2* in = zp + (size_t)l * zs + (size_t)N2 * n1 * Nh;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int k2 = e / W, c = e % W;
+    buf[e] = in[(size_t)k2 * Nh + c0 + c];
+  }
+  __syncthreads();
+  fft_run<N2, W, NT, true, 1, N1>(buf, tw);
+  float* xo = x + (size_t)l * Ny * Nx;
+  for (int e = threadIdx.x; e < N2 * W; e += NT) {
+    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+    const int p = (n < N / 2 ? n : n - N) + Ny / 2;
+    if (p >= 0 && p < Ny) {
+      const int q = 2 * (c0 + c);
+      const float s = sy[p];
+      const float2 v = buf[e];
+      *reinterpret_cast<float2*>(xo + (size_t)p * Nx + q) = make_float2(s * sx[q] * v.x, s * sx[q + 1] * v.y);
+    }
+  }
+}
+
 // ------------------------------------------------------------ G (gather)
 // Raw G storage per precision: complex float, or two 16-bit halves in a word.
 template <int GP>
@@ -2103,6 +2332,55 @@ hipError_t colfft_inv_n(const float2* grid, float2* half, const float2* tw, int 
   return hipGetLastError();
 }
 
+// Packed-column panel width of the image-first transform for an image width
+// Nx (Nx / 2 packed columns), or 0 when the transform runs rows first.
+inline int colr_width(int Nx) { return (Nx / 2) % 32 == 0 ? 32 : (Nx / 2) % 8 == 0 ? 8 : 0; }
+
+template <int N, int W>
+hipError_t colr_fwd_nw(const float* x, float2* zp, float2* T, const float* sy, const float* sx, const float2* tw,
+                       int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  constexpr int N1 = col_split1<N>(), N2 = N / N1;
+  constexpr int TA = panel_threads<N2 * W>(), TB = panel_threads<N1 * 2 * W>();
+  const int npc = (Nx / 2) / W;
+  const size_t zs = (size_t)N * 2 * Nx;  // each channel's packed columns in its own grid region
+  hipLaunchKernelGGL((k_colr_fwd_a<N1, N2, W, TA>), dim3(N1 * npc, nl), dim3(TA), 0, s, x, zp, sy, sx, tw, Ny, Nx, l0,
+                     zs);
+  hipLaunchKernelGGL((k_colr_fwd_b<N1, N2, W, TB>), dim3((N2 / 2 + 1) * npc, nl), dim3(TB), 0, s, zp, T, tw, Nx, l0,
+                     zs);
+  return hipGetLastError();
+}
+template <int N, int W>
+hipError_t colr_inv_nw(const float2* T, float2* zp, float* x, const float* sy, const float* sx, const float2* tw,
+                       int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  constexpr int N1 = col_split1<N>(), N2 = N / N1;
+  constexpr int TA = panel_threads<N2 * W>(), TB = panel_threads<N1 * 2 * W>();
+  const int npc = (Nx / 2) / W;
+  const size_t zs = (size_t)N * 2 * Nx;  // each channel's packed columns in its own grid region
+  hipLaunchKernelGGL((k_colr_inv_b<N1, N2, W, TB>), dim3((N2 / 2 + 1) * npc, nl), dim3(TB), 0, s, T, zp, tw, Nx, l0,
+                     zs);
+  hipLaunchKernelGGL((k_colr_inv_a<N1, N2, W, TA>), dim3(N1 * npc, nl), dim3(TA), 0, s, zp, x, sy, sx, tw, Ny, Nx, l0,
+                     zs);
+  return hipGetLastError();
+}
+
+// Row passes of the image-first transform (Kx = N, Nx = N / 2).
+template <int N>
+constexpr int rowc_threads() {
+  return N / 8 < 64 ? 64 : N / 8 > 1024 ? 1024 : N / 8;
+}
+template <int N>
+hipError_t rowc_fwd_n(const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+  hipLaunchKernelGGL((k_rowc_fwd<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, T, grid, tw, Ky,
+                     l0);
+  return hipGetLastError();
+}
+template <int N>
+hipError_t rowc_inv_n(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+  hipLaunchKernelGGL((k_rowc_inv<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, grid, T, tw, Ky,
+                     l0);
+  return hipGetLastError();
+}
+
 #define PHI_FFT_SIZES(X)                                                                              \
   X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(640) X(768) X(1024) X(1280) X(1536) \
       X(2048) X(2560) X(3072) X(4096) X(5120) X(6144) X(8192)
@@ -2382,6 +2660,71 @@ hipError_t launch_dr_setup(const DrArgs& a, int n_groups, hipStream_t s) {
   if (n_groups <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dr_setup, dim3(n_groups), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// Image-first 2-D transform (grids with two-pass columns): see k_colr_fwd_a.
+bool fft_image_first(int Ky, int Nx) {
+  switch (Ky) {
+    case 3072: case 4096: case 5120: case 6144: case 8192:
+      return colr_width(Nx) > 0;
+    default:
+      return false;
+  }
+}
+
+#define PHI_COLR_SIZES(X) X(3072) X(4096) X(5120) X(6144) X(8192)
+
+hipError_t launch_colr_fwd(int Ky, const float* x, float2* zp, float2* T, const float* sy, const float* sx,
+                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  const int W = colr_width(Nx);
+  switch (Ky) {
+#define X(N)                                                                                   \
+  case N:                                                                                      \
+    return W == 32 ? colr_fwd_nw<N, 32>(x, zp, T, sy, sx, tw, Ny, Nx, l0, nl, s)               \
+           : W == 8 ? colr_fwd_nw<N, 8>(x, zp, T, sy, sx, tw, Ny, Nx, l0, nl, s) : hipErrorInvalidValue;
+    PHI_COLR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_colr_inv(int Ky, const float2* T, float2* zp, float* x, const float* sy, const float* sx,
+                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s) {
+  const int W = colr_width(Nx);
+  switch (Ky) {
+#define X(N)                                                                                   \
+  case N:                                                                                      \
+    return W == 32 ? colr_inv_nw<N, 32>(T, zp, x, sy, sx, tw, Ny, Nx, l0, nl, s)               \
+           : W == 8 ? colr_inv_nw<N, 8>(T, zp, x, sy, sx, tw, Ny, Nx, l0, nl, s) : hipErrorInvalidValue;
+    PHI_COLR_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_rowc_fwd(int Kx, const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl,
+                           hipStream_t s) {
+  switch (Kx) {
+#define X(N) \
+  case N:    \
+    return rowc_fwd_n<N>(T, grid, tw, Ky, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+hipError_t launch_rowc_inv(int Kx, const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl,
+                           hipStream_t s) {
+  switch (Kx) {
+#define X(N) \
+  case N:    \
+    return rowc_inv_n<N>(grid, T, tw, Ky, l0, nl, s);
+    PHI_FFT_SIZES(X)
+#undef X
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace phi
