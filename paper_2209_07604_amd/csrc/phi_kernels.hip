@@ -202,9 +202,17 @@ constexpr int pick_radix(int rem) {
                         : 2;
 }
 
+// LDS slot of element i of a padded buffer: one spare slot after every 16,
+// so the strided writes of the first passes of a transform over one or two
+// sequences (lanes 8 or 16 elements apart) do not pile onto a few banks.
+template <bool PAD>
+__device__ __forceinline__ int lds_i(int i) {
+  return PAD ? i + (i >> 4) : i;
+}
+
 // tw holds the twiddles exp(-2 pi i m / (N TS)); a sub-transform of length N
-// reads every TS-th one.
-template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1>
+// reads every TS-th one.  PAD: buf is addressed through lds_i.
+template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1, bool PAD = false>
 __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw) {
   constexpr int STRIDE = N / R;
   constexpr int NB = STRIDE * W;
@@ -218,7 +226,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
     if (NB % NT == 0 || j < NB) {
       const int c = j % W, b = j / W;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[(b + r * STRIDE) * W + c];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[lds_i<PAD>((b + r * STRIDE) * W + c)];
       if constexpr (NS > 1) {
         const int k = b % NS;
 #pragma unroll
@@ -240,18 +248,18 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
       dft<R, INV>(v[q]);
       const int d = (b / NS) * NS * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(d + r * NS) * W + c] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[lds_i<PAD>((d + r * NS) * W + c)] = v[q][r];
     }
   }
   __syncthreads();
 }
 
-template <int N, int W, int NT, bool INV, int NS, int TS = 1>
+template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false>
 __device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS);
-    fft_pass<N, W, NT, INV, R, NS, TS>(buf, tw);
-    fft_run<N, W, NT, INV, NS * R, TS>(buf, tw);
+    fft_pass<N, W, NT, INV, R, NS, TS, PAD>(buf, tw);
+    fft_run<N, W, NT, INV, NS * R, TS, PAD>(buf, tw);
   }
 }
 
@@ -266,7 +274,7 @@ __global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, 
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
   constexpr int M = N / 2;
-  __shared__ float2 buf[M];
+  __shared__ float2 buf[M + M / 16];
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
@@ -274,12 +282,12 @@ __global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, 
     const int q = (n < N / 2 ? n : n - N) + Nx / 2;
     return (q >= 0 && q < Nx) ? syp * sx[q] * xr[q] : 0.f;
   };
-  for (int m = threadIdx.x; m < M; m += NT) buf[m] = make_float2(sample(2 * m), sample(2 * m + 1));
+  for (int m = threadIdx.x; m < M; m += NT) buf[lds_i<true>(m)] = make_float2(sample(2 * m), sample(2 * m + 1));
   __syncthreads();
-  fft_run<M, 1, NT, false, 1, 2>(buf, tw);
+  fft_run<M, 1, NT, false, 1, 2, true>(buf, tw);
   float2* out = half + ((size_t)l * Ny + p) * N;
   for (int kk = threadIdx.x; kk < M; kk += NT) {
-    const float2 a = buf[kk], b = buf[kk == 0 ? 0 : M - kk];
+    const float2 a = buf[lds_i<true>(kk)], b = buf[lds_i<true>(kk == 0 ? 0 : M - kk)];
     const float2 e = make_float2(0.5f * (a.x + b.x), 0.5f * (a.y - b.y));  // (Z[k] + conj(Z[-k])) / 2
     const float2 o = make_float2(0.5f * (a.y + b.y), 0.5f * (b.x - a.x));  // (Z[k] - conj(Z[-k])) / (2i)
     const float2 wo = cmul(tw[kk], o);
@@ -299,7 +307,7 @@ __global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ ha
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
   constexpr int M = N / 2;
-  __shared__ float2 buf[M];
+  __shared__ float2 buf[M + M / 16];
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float2* in = half + ((size_t)l * Ny + p) * N;
   auto herm = [&](int k) {  // Hs[k]
@@ -312,16 +320,16 @@ __global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ ha
     float2 w = tw[kk];
     w.y = -w.y;  // w^-k
     const float2 fo = cmul(make_float2(h0.x - h1.x, h0.y - h1.y), w);
-    buf[kk] = make_float2(fe.x - fo.y, fe.y + fo.x);  // Fe + i Fo
+    buf[lds_i<true>(kk)] = make_float2(fe.x - fo.y, fe.y + fo.x);  // Fe + i Fo
   }
   __syncthreads();
-  fft_run<M, 1, NT, true, 1, 2>(buf, tw);
+  fft_run<M, 1, NT, true, 1, 2, true>(buf, tw);
   float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
   for (int q = threadIdx.x; q < Nx; q += NT) {
     int n = q - Nx / 2;
     if (n < 0) n += N;
-    const float2 z = buf[n >> 1];
+    const float2 z = buf[lds_i<true>(n >> 1)];
     xr[q] = ((n & 1) ? z.y : z.x) * syp * sx[q];
   }
 }
@@ -551,7 +559,7 @@ template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_rowc_fwd(const float2* __restrict__ T, float2* __restrict__ grid,
                                                  const float2* __restrict__ tw, int Ky, int l0) {
   constexpr int M = N / 2, Nx = M;
-  __shared__ float2 buf[N];
+  __shared__ float2 buf[N + N / 16];  // padded
   const int k = blockIdx.x, l = l0 + blockIdx.y;
   const float2* t = T + ((size_t)l * Ky + k) * Nx;
   for (int m = threadIdx.x; m < M; m += NT) {
@@ -559,14 +567,16 @@ __global__ __launch_bounds__(NT) void k_rowc_fwd(const float2* __restrict__ T, f
     const float2 u = t[lo ? m + Nx / 2 : m - Nx / 2];
     const float2 w = tw[m];
     const float2 uw = cmul(u, w);
-    buf[2 * m] = u;
-    buf[2 * m + 1] = lo ? uw : make_float2(-uw.x, -uw.y);
+    buf[lds_i<true>(2 * m)] = u;
+    buf[lds_i<true>(2 * m + 1)] = lo ? uw : make_float2(-uw.x, -uw.y);
   }
   __syncthreads();
-  fft_run<M, 2, NT, false, 1, 2>(buf, tw);
+  fft_run<M, 2, NT, false, 1, 2, true>(buf, tw);
   float4* out = reinterpret_cast<float4*>(grid + ((size_t)l * Ky + k) * N);
-  const float4* b4 = reinterpret_cast<const float4*>(buf);
-  for (int i = threadIdx.x; i < M; i += NT) out[i] = b4[i];
+  for (int i = threadIdx.x; i < M; i += NT) {
+    const float2 a = buf[lds_i<true>(2 * i)], b = buf[lds_i<true>(2 * i + 1)];
+    out[i] = make_float4(a.x, a.y, b.x, b.y);
+  }
 }
 
 // Row pass (inverse): grid row k to row k of T' (the Nx kept columns):
@@ -576,20 +586,23 @@ template <int N, int NT>
 __global__ __launch_bounds__(NT) void k_rowc_inv(const float2* __restrict__ grid, float2* __restrict__ T,
                                                  const float2* __restrict__ tw, int Ky, int l0) {
   constexpr int M = N / 2, Nx = M;
-  __shared__ float2 buf[N];
+  __shared__ float2 buf[N + N / 16];  // padded
   const int k = blockIdx.x, l = l0 + blockIdx.y;
   const float4* in = reinterpret_cast<const float4*>(grid + ((size_t)l * Ky + k) * N);
-  float4* b4 = reinterpret_cast<float4*>(buf);
-  for (int i = threadIdx.x; i < M; i += NT) b4[i] = in[i];
+  for (int i = threadIdx.x; i < M; i += NT) {
+    const float4 v = in[i];
+    buf[lds_i<true>(2 * i)] = make_float2(v.x, v.y);
+    buf[lds_i<true>(2 * i + 1)] = make_float2(v.z, v.w);
+  }
   __syncthreads();
-  fft_run<M, 2, NT, true, 1, 2>(buf, tw);
+  fft_run<M, 2, NT, true, 1, 2, true>(buf, tw);
   float2* t = T + ((size_t)l * Ky + k) * Nx;
   for (int q = threadIdx.x; q < Nx; q += NT) {
     const bool hi = q >= Nx / 2;
     const int n = hi ? q - Nx / 2 : q - Nx / 2 + N, m = hi ? q - Nx / 2 : q + Nx / 2;
     float2 w = tw[n];
     w.y = -w.y;
-    const float2 o = cmul(buf[2 * m + 1], w), e = buf[2 * m];
+    const float2 o = cmul(buf[lds_i<true>(2 * m + 1)], w), e = buf[lds_i<true>(2 * m)];
     t[q] = make_float2(e.x + o.x, e.y + o.y);
   }
 }
@@ -2370,14 +2383,14 @@ constexpr int rowc_threads() {
 }
 template <int N>
 hipError_t rowc_fwd_n(const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowc_fwd<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, T, grid, tw, Ky,
-                     l0);
+  hipLaunchKernelGGL((k_rowc_fwd<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, T, grid,
+                     tw, Ky, l0);
   return hipGetLastError();
 }
 template <int N>
 hipError_t rowc_inv_n(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowc_inv<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, grid, T, tw, Ky,
-                     l0);
+  hipLaunchKernelGGL((k_rowc_inv<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, grid,
+                     T, tw, Ky, l0);
   return hipGetLastError();
 }
 
