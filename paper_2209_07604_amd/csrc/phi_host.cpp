@@ -291,6 +291,24 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   }
   w.halo = (p->smax - 1 + T - 1) / T;
   if (w.halo < 1) w.halo = 1;
+  // live tiles: those whose merge list (their own partials and those of the
+  // tiles up to `halo` above / left, with wrap) is not empty
+  w.live.clear();
+  w.chan_live0.assign(p->L + 1, 0);
+  for (int l = 0; l < p->L; ++l) {
+    for (int ty = 0; ty < nty; ++ty)
+      for (int tx = 0; tx < ntx; ++tx) {
+        bool any = false;
+        for (int dy = 0; dy <= w.halo && !any; ++dy)
+          for (int dx = 0; dx <= w.halo && !any; ++dx) {
+            const int sty = ((ty - dy) % nty + nty) % nty, stx = ((tx - dx) % ntx + ntx) % ntx;
+            const int64_t t = ((int64_t)l * nty + sty) * ntx + stx;
+            any = w.tile_ptr[t + 1] > w.tile_ptr[t];
+          }
+        if (any) w.live.push_back((int32_t)(((int64_t)l * nty + ty) * ntx + tx));
+      }
+    w.chan_live0[l + 1] = (int32_t)w.live.size();
+  }
 }
 
 bool phi_plan_s::fused() const {
@@ -312,12 +330,14 @@ static void layout(phi_plan_s* p, size_t base = 0, const phi_plan_s* share = nul
   p->off_frac = take(p->gprec == PHI_G_KB ? (size_t)p->M * 8 : 0);  // (kappa - b) per visibility, FP32
   p->off_meta = take((size_t)p->M * 4);
   p->off_perm = take((size_t)p->M * 4);
-  size_t n_items = 0, n_tptr = 0, n_part = 0;
+  size_t n_items = 0, n_tptr = 0, n_part = 0, n_live = 0;
   for (const WorkList& w : p->cands) {
     n_items = std::max(n_items, w.items.size());
     n_tptr = std::max(n_tptr, w.tile_ptr.size());
     n_part = std::max(n_part, (size_t)w.partial_elems);
+    n_live = std::max(n_live, w.live.size());
   }
+  p->off_live = take(n_live * 4);
   p->off_items = take(n_items * sizeof(Item));
   p->off_items_p = take(n_items * sizeof(Item));
   p->off_binfo = take((size_t)p->nblk * sizeof(BlockInfo));
@@ -332,7 +352,10 @@ static void layout(phi_plan_s* p, size_t base = 0, const phi_plan_s* share = nul
   p->off_bpart = take((size_t)p->nblk * kFinChunks * 16);  // per-block chunk sums of the item norms
   p->off_flag = take(16);
   if (share) {
+    // a reduced plan's adjoint runs through the shared grid, every tile written
     p->off_grid = share->off_grid;
+    p->off_grid_a = share->off_grid;
+    p->sparse_merge = false;
     p->off_half = share->off_half;
     p->off_twx = share->off_twx;
     p->off_twy = share->off_twy;
@@ -340,6 +363,9 @@ static void layout(phi_plan_s* p, size_t base = 0, const phi_plan_s* share = nul
     p->off_sx = share->off_sx;
   } else {
     p->off_grid = take((size_t)p->L * p->Ky * p->Kx * 8);
+    // an adjoint grid of its own where the inverse transform only reads it
+    p->sparse_merge = fft_inverse_reads_grid_only(p->Ky, p->Nx);
+    p->off_grid_a = p->sparse_merge ? take((size_t)p->L * p->Ky * p->Kx * 8) : p->off_grid;
     p->off_half = take((size_t)p->L * p->Ny * p->Kx * 8);
     p->off_twx = take((size_t)p->Kx * 8);
     p->off_twy = take((size_t)p->Ky * 8);
@@ -361,6 +387,11 @@ static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
   up(p->off_binfo, w.binfo.data(), w.binfo.size() * sizeof(BlockInfo));
   up(p->off_tptr, w.tile_ptr.data(), w.tile_ptr.size() * 4);
   up(p->off_ent, w.entries.data(), w.entries.size() * sizeof(TileEntry));
+  up(p->off_live, w.live.data(), w.live.size() * 4);
+  // the adjoint grid starts at zero: the merge of this tiling writes only
+  // its live tiles, and no window reaches the others' cells
+  if (e == hipSuccess && p->sparse_merge)
+    e = hipMemsetAsync(p->ws + p->off_grid_a, 0, (size_t)p->L * p->Ky * p->Kx * 8, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   return e;
 }
@@ -900,19 +931,25 @@ struct Runner {
                                p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);
     });
   }
+  // The merge of channels [l0, l1) into the adjoint grid: the live tiles
+  // only (sparse merge), else every tile.
+  hipError_t merge(int l0, int l1, const double* msig, const double* mscale) const {
+    const WorkList& w = p->W();
+    const int32_t* live = p->sparse_merge ? p->at<int32_t>(p->off_live) : nullptr;
+    const int lb = live ? w.chan_live0[l0] : 0, ln = live ? w.chan_live0[l1] - w.chan_live0[l0] : 0;
+    return launch_merge(p->at<float2>(p->off_grid_a), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
+                        p->at<TileEntry>(p->off_ent), live, lb, ln, p->Ky, p->Kx, w.T, w.halo, l0, l1 - l0, msig,
+                        mscale, s);
+  }
   // msig / mscale: per-block merge factors after the fused dual step (null: 1)
   void adj_fft(float* x, int l0, int l1, const double* msig = nullptr, const double* mscale = nullptr) {
     const int nl = l1 - l0;
-    stage(5, [&] {
-      return launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                          p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, l0, nl, msig, mscale,
-                          s);
-    });
+    stage(5, [&] { return merge(l0, l1, msig, mscale); });
     if (fft_image_first(p->Ky, p->Nx)) {
       // rows first (the Nx kept columns into the half grid), then the image's
       // columns (packed columns in the grid buffer), real part, Z^T
       stage(7, [&] {
-        return launch_rowc_inv(p->Kx, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
+        return launch_rowc_inv(p->Kx, p->at<float2>(p->off_grid_a), p->at<float2>(p->off_half),
                                p->at<float2>(p->off_twx), p->Ky, l0, nl, s);
       });
       stage(6, [&] {
@@ -923,7 +960,7 @@ struct Runner {
       return;
     }
     stage(6, [&] {
-      return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid), p->at<float2>(p->off_half),
+      return launch_colfft_inv(p->Ky, p->at<float2>(p->off_grid_a), p->at<float2>(p->off_half),
                                p->at<float2>(p->off_twy), p->Ny, p->Kx, l0, nl, s);
     });
     stage(7, [&] {
@@ -1203,10 +1240,7 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
       if (fused && r.err == hipSuccess) r.err = r.gather(2, a, vs, vs, 0, p->L);
       if (!fused && g && r.err == hipSuccess) r.err = r.gather(0, a, vs, nullptr, 0, p->L);
       if (!fused && sc && r.err == hipSuccess) r.err = r.scatter(0, a, vs, 0, p->L);
-      if ((sc || fused) && r.err == hipSuccess)
-        r.err = launch_merge(p->at<float2>(p->off_grid), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                             p->at<TileEntry>(p->off_ent), p->Ky, p->Kx, p->W().T, p->W().halo, 0, p->L, nullptr,
-                             nullptr, s);
+      if ((sc || fused) && r.err == hipSuccess) r.err = r.merge(0, p->L, nullptr, nullptr);
     };
     once();
     (void)hipEventRecord(e0, s);

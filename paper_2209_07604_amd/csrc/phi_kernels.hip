@@ -18,6 +18,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include "phi_internal.h"
 
 namespace phi {
@@ -211,14 +213,20 @@ __device__ __forceinline__ int lds_i(int i) {
 }
 
 // tw holds the twiddles exp(-2 pi i m / (N TS)); a sub-transform of length N
-// reads every TS-th one.  PAD: buf is addressed through lds_i.
-template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1, bool PAD = false>
-__device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw) {
+// reads every TS-th one.  PAD: buf is addressed through lds_i.  REG: the
+// twiddles come from tab, an LDS table of the pass's base twiddles
+// w = exp(-+2 pi i k / (NS R)), k < NS (tw_table), as w^r by squarings and
+// one product per odd r (a few ulp from the table's values), so the pass
+// issues no global load.
+// tid: the thread's index (threadIdx.x; a loop over transforms passes a copy
+// the compiler cannot see through, so the LDS addresses are formed in the
+// loop instead of being hoisted out of it and held in registers).
+template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1, bool PAD = false, bool REG = false>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw, const float2* tab, int tid) {
   constexpr int STRIDE = N / R;
   constexpr int NB = STRIDE * W;
   constexpr int BPT = (NB + NT - 1) / NT;
   constexpr int TWS = N / (NS * R);
-  const int tid = threadIdx.x;
   float2 v[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -227,7 +235,15 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
       const int c = j % W, b = j / W;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = buf[lds_i<PAD>((b + r * STRIDE) * W + c)];
-      if constexpr (NS > 1) {
+      if constexpr (NS > 1 && REG) {
+        float2 w[R];
+        w[1] = tab[b % NS];
+        if (INV) w[1].y = -w[1].y;
+#pragma unroll
+        for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
+      } else if constexpr (NS > 1) {
         const int k = b % NS;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -254,12 +270,39 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
   __syncthreads();
 }
 
-template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false>
-__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
+template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false, bool REG = false>
+__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw, const float2* tab, int tid) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS);
-    fft_pass<N, W, NT, INV, R, NS, TS, PAD>(buf, tw);
-    fft_run<N, W, NT, INV, NS * R, TS, PAD>(buf, tw);
+    fft_pass<N, W, NT, INV, R, NS, TS, PAD, REG>(buf, tw, tab, tid);
+    fft_run<N, W, NT, INV, NS * R, TS, PAD, REG>(buf, tw, REG && NS > 1 ? tab + NS : tab, tid);
+  }
+}
+template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false>
+__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
+  fft_run<N, W, NT, INV, NS, TS, PAD, false>(buf, tw, nullptr, (int)threadIdx.x);
+}
+
+// Base twiddle table of fft_run<..., REG = true>: NS entries per twiddled
+// pass, tw_table_size in all.
+constexpr int tw_table_size(int N) {
+  int s = 0;
+  for (int NS = 1; NS < N;) {
+    if (NS > 1) s += NS;
+    NS *= pick_radix(N / NS);
+  }
+  return s;
+}
+template <int N, int NT, int NS, int TS>
+__device__ __forceinline__ void tw_table(float2* tab, const float2* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int R = pick_radix(N / NS), TWS = N / (NS * R);
+    if constexpr (NS > 1) {
+      for (int k = threadIdx.x; k < NS; k += NT) tab[k] = tw[k * TWS * TS];
+      tw_table<N, NT, NS * R, TS>(tab + NS, tw);
+    } else {
+      tw_table<N, NT, NS * R, TS>(tab, tw);
+    }
   }
 }
 
@@ -550,60 +593,143 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp
   }
 }
 
-// Row pass (forward): row k of T (Nx values, centred in Kx = N cells) to
+// Row passes.  Forward: row k of T (Nx values, centred in Kx = N cells) to
 // grid row k.  Input cell n is nonzero for n < Nx/2 or n >= N - Nx/2, so
 // with M = N/2 = Nx: X[2k'] = DFT_M(u)[k'], X[2k'+1] = DFT_M(v)[k'] with
 // u[m] = T[(m + Nx/2) mod Nx] and v[m] = +-u[m] w_N^m (minus for m >= Nx/2);
 // u and v run interleaved, so the transformed buffer is the grid row.
+// Inverse: grid row k to row k of T' (the Nx kept columns):
+// x[n] = E[n mod M] + w_N^-n O[n mod M] with E, O the inverse DFTs of the
+// even and odd samples, run interleaved.
+//
+// Both are persistent: a work-group loops over rows r = blockIdx.x +
+// i gridDim.x of the nl Ky rows, with its pass twiddles in an LDS table
+// (fft_run<REG>), and loads row r + gridDim.x into registers before it
+// transforms row r, so the loads of one row overlap the LDS passes and the
+// stores of the other.  w^m of the load (w^-n of the store) is w^tid times
+// a uniform table entry (the inverse takes w^tid from an LDS table of the 64
+// lane values and a uniform entry, to keep its registers for the prefetch).
+template <int N>
+constexpr int rowc_threads() {
+  return N / 8 < 64 ? 64 : N / 8 > 1024 ? 1024 : N / 8;
+}
+// Waves per SIMD the LDS allows (160 KiB per CU, 8 waves per SIMD at most):
+// the register budget the long rows are compiled for.
 template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_rowc_fwd(const float2* __restrict__ T, float2* __restrict__ grid,
-                                                 const float2* __restrict__ tw, int Ky, int l0) {
-  constexpr int M = N / 2, Nx = M;
+constexpr int rowc_waves() {
+  constexpr int waves = (NT + 63) / 64, lds = (N + N / 16) * 8;
+  constexpr int wgs = 163840 / lds < 32 / waves ? 163840 / lds : 32 / waves;
+  constexpr int w = wgs * waves / 4;
+  return N < 2048 ? 1 : w < 1 ? 1 : w > 8 ? 8 : w;
+}
+template <int N, int NT>
+__global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_fwd_p(const float2* __restrict__ T,
+                                                                   float2* __restrict__ grid,
+                                                                   const float2* __restrict__ tw, int Ky, int l0,
+                                                                   int nrows) {
+  constexpr int M = N / 2, Nx = M, PT = (M + NT - 1) / NT, NW = tw_table_size(M);
   __shared__ float2 buf[N + N / 16];  // padded
-  const int k = blockIdx.x, l = l0 + blockIdx.y;
-  const float2* t = T + ((size_t)l * Ky + k) * Nx;
-  for (int m = threadIdx.x; m < M; m += NT) {
-    const bool lo = m < Nx / 2;
-    const float2 u = t[lo ? m + Nx / 2 : m - Nx / 2];
-    const float2 w = tw[m];
-    const float2 uw = cmul(u, w);
-    buf[lds_i<true>(2 * m)] = u;
-    buf[lds_i<true>(2 * m + 1)] = lo ? uw : make_float2(-uw.x, -uw.y);
-  }
-  __syncthreads();
-  fft_run<M, 2, NT, false, 1, 2, true>(buf, tw);
-  float4* out = reinterpret_cast<float4*>(grid + ((size_t)l * Ky + k) * N);
-  for (int i = threadIdx.x; i < M; i += NT) {
-    const float2 a = buf[lds_i<true>(2 * i)], b = buf[lds_i<true>(2 * i + 1)];
-    out[i] = make_float4(a.x, a.y, b.x, b.y);
+  __shared__ float2 tab[NW > 0 ? NW : 1];
+  const int tid = threadIdx.x;
+  tw_table<M, NT, 1, 2>(tab, tw);
+  const float2 wb = tid < N ? tw[tid] : make_float2(1.f, 0.f);  // w^tid
+  float2 u[PT];
+  auto load = [&](int r) {
+    const int l = l0 + r / Ky, k = r % Ky;
+    const float2* t = T + ((size_t)l * Ky + k) * Nx;
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int m = tid + q * NT;
+      if (M % NT == 0 || m < M) u[q] = t[m < Nx / 2 ? m + Nx / 2 : m - Nx / 2];
+    }
+  };
+  int r = blockIdx.x;
+  if (r < nrows) load(r);
+  for (; r < nrows; r += gridDim.x) {
+    // per-iteration copies the compiler cannot see through (see fft_pass)
+    int tl = tid;
+    float2 wl = wb;
+    asm volatile("" : "+v"(tl), "+v"(wl.x), "+v"(wl.y));
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int m = tl + q * NT;
+      if (M % NT == 0 || m < M) {
+        const float2 uw = cmul(u[q], cmul(wl, tw[q * NT]));
+        buf[lds_i<true>(2 * m)] = u[q];
+        buf[lds_i<true>(2 * m + 1)] = m < Nx / 2 ? uw : make_float2(-uw.x, -uw.y);
+      }
+    }
+    if (r + (int)gridDim.x < nrows) load(r + gridDim.x);
+    __syncthreads();
+    fft_run<M, 2, NT, false, 1, 2, true, true>(buf, tw, tab, tl);
+    const int l = l0 + r / Ky, k = r % Ky;
+    float4* out = reinterpret_cast<float4*>(grid + ((size_t)l * Ky + k) * N);
+    for (int i = tl; i < M; i += NT) {
+      const float2 a = buf[lds_i<true>(2 * i)], b = buf[lds_i<true>(2 * i + 1)];
+      out[i] = make_float4(a.x, a.y, b.x, b.y);
+    }
+    __syncthreads();
   }
 }
 
-// Row pass (inverse): grid row k to row k of T' (the Nx kept columns):
-// x[n] = E[n mod M] + w_N^-n O[n mod M] with E, O the inverse DFTs of the
-// even and odd samples, run interleaved.
 template <int N, int NT>
-__global__ __launch_bounds__(NT) void k_rowc_inv(const float2* __restrict__ grid, float2* __restrict__ T,
-                                                 const float2* __restrict__ tw, int Ky, int l0) {
-  constexpr int M = N / 2, Nx = M;
+__global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_inv_p(const float2* __restrict__ grid,
+                                                                   float2* __restrict__ T,
+                                                                   const float2* __restrict__ tw, int Ky, int l0,
+                                                                   int nrows) {
+  constexpr int M = N / 2, Nx = M, PT = (M + NT - 1) / NT, NW = tw_table_size(M);
   __shared__ float2 buf[N + N / 16];  // padded
-  const int k = blockIdx.x, l = l0 + blockIdx.y;
-  const float4* in = reinterpret_cast<const float4*>(grid + ((size_t)l * Ky + k) * N);
-  for (int i = threadIdx.x; i < M; i += NT) {
-    const float4 v = in[i];
-    buf[lds_i<true>(2 * i)] = make_float2(v.x, v.y);
-    buf[lds_i<true>(2 * i + 1)] = make_float2(v.z, v.w);
-  }
-  __syncthreads();
-  fft_run<M, 2, NT, true, 1, 2, true>(buf, tw);
-  float2* t = T + ((size_t)l * Ky + k) * Nx;
-  for (int q = threadIdx.x; q < Nx; q += NT) {
-    const bool hi = q >= Nx / 2;
-    const int n = hi ? q - Nx / 2 : q - Nx / 2 + N, m = hi ? q - Nx / 2 : q + Nx / 2;
-    float2 w = tw[n];
-    w.y = -w.y;
-    const float2 o = cmul(buf[lds_i<true>(2 * m + 1)], w), e = buf[lds_i<true>(2 * m)];
-    t[q] = make_float2(e.x + o.x, e.y + o.y);
+  __shared__ float2 tab[NW > 0 ? NW : 1];
+  __shared__ float2 s_lane[64];  // w^lane
+  const int tid = threadIdx.x;
+  tw_table<M, NT, 1, 2>(tab, tw);
+  if (tid < 64) s_lane[tid] = tid < N ? tw[tid] : make_float2(1.f, 0.f);
+  float4 v[PT];
+  auto load = [&](int r) {
+    const int l = l0 + r / Ky, k = r % Ky;
+    const float4* in = reinterpret_cast<const float4*>(grid + ((size_t)l * Ky + k) * N);
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int i = tid + q * NT;
+      if (M % NT == 0 || i < M) v[q] = in[i];
+    }
+  };
+  int r = blockIdx.x;
+  if (r < nrows) load(r);
+  for (; r < nrows; r += gridDim.x) {
+    // per-iteration copy the compiler cannot see through (see fft_pass)
+    int tl = tid;
+    asm volatile("" : "+v"(tl));
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int i = tl + q * NT;
+      if (M % NT == 0 || i < M) {
+        buf[lds_i<true>(2 * i)] = make_float2(v[q].x, v[q].y);
+        buf[lds_i<true>(2 * i + 1)] = make_float2(v[q].z, v[q].w);
+      }
+    }
+    if (r + (int)gridDim.x < nrows) load(r + gridDim.x);
+    __syncthreads();
+    fft_run<M, 2, NT, true, 1, 2, true, true>(buf, tw, tab, tl);
+    const int l = l0 + r / Ky, k = r % Ky;
+    float2* t = T + ((size_t)l * Ky + k) * Nx;
+    // w^-tid = conj(w^lane w^wave_base): an LDS entry and a uniform (scalar) load
+    const int wbase = __builtin_amdgcn_readfirstlane(tl & ~63);
+    float2 wl = cmul(s_lane[tl & 63], tw[wbase < N ? wbase : 0]);
+    wl.y = -wl.y;
+#pragma unroll
+    for (int q = 0; q < PT; ++q) {
+      const int c = tl + q * NT;
+      if (Nx % NT == 0 || c < Nx) {
+        // x[c] = E[m] + w^-n O[m]: n = (c - Nx/2) mod N, m = n mod M
+        const int m = c >= Nx / 2 ? c - Nx / 2 : c + Nx / 2;
+        float2 wu = tw[((q * NT - Nx / 2) % N + N) % N];
+        wu.y = -wu.y;
+        const float2 o = cmul(buf[lds_i<true>(2 * m + 1)], cmul(wl, wu)), e = buf[lds_i<true>(2 * m)];
+        t[c] = make_float2(e.x + o.x, e.y + o.y);
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1656,17 +1782,22 @@ __device__ __forceinline__ float merge_factor(const double* sigma, const double*
 
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
-                                               const TileEntry* __restrict__ ent, int Ky, int Kx, int T,
-                                               int halo, int l0, const double* __restrict__ sigma,
-                                               const double* __restrict__ scale) {
+                                               const TileEntry* __restrict__ ent, const int32_t* __restrict__ live,
+                                               int live0, int Ky, int Kx, int T, int halo, int l0,
+                                               const double* __restrict__ sigma, const double* __restrict__ scale) {
   __shared__ int64_t s_off[kMergeList];
   __shared__ int32_t s_pitch[kMergeList];
   __shared__ float s_fac[kMergeList];
   __shared__ int32_t s_oy[kMergeList], s_ox[kMergeList];
   __shared__ int s_beg[16], s_pre[17];
-  const int l = l0 + blockIdx.y;
   const int nty = Ky / T, ntx = Kx / T;
-  const int ty = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+  int l = l0 + blockIdx.y, tile_i = blockIdx.x;
+  if (live) {
+    const int t = live[live0 + blockIdx.x];
+    l = t / (nty * ntx);
+    tile_i = t % (nty * ntx);
+  }
+  const int ty = tile_i / ntx, tx = tile_i % ntx;
   const int hw = halo + 1, nsrc = hw * hw;   // halo <= 3: at most 16 source tiles
   if ((int)threadIdx.x < nsrc) {
     const int dy = threadIdx.x / hw, dx = threadIdx.x % hw;
@@ -2377,21 +2508,51 @@ hipError_t colr_inv_nw(const float2* T, float2* zp, float* x, const float* sy, c
 }
 
 // Row passes of the image-first transform (Kx = N, Nx = N / 2).
-template <int N>
-constexpr int rowc_threads() {
-  return N / 8 < 64 ? 64 : N / 8 > 1024 ? 1024 : N / 8;
+// Resident work-groups of a persistent kernel over the current device (its
+// occupancy per CU times the CU count); `cache` holds one value per device.
+template <typename K>
+int resident_groups(K kernel, int threads, int* cache) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess)
+      return 0;
+    cache[dev] = std::max(1, per_cu) * std::max(1, cus);
+  }
+  return cache[dev];
+}
+template <int N, int NT>
+hipError_t rowc_fwd_nt(const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+  static int cache[64] = {0};
+  const int g = resident_groups(k_rowc_fwd_p<N, NT>, NT, cache);
+  if (g <= 0) return hipErrorInvalidDevice;
+  const int nrows = Ky * nl;
+  hipLaunchKernelGGL((k_rowc_fwd_p<N, NT>), dim3(std::min(g, nrows)), dim3(NT), 0, s, T, grid, tw, Ky, l0, nrows);
+  return hipGetLastError();
+}
+template <int N, int NT>
+hipError_t rowc_inv_nt(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+  static int cache[64] = {0};
+  const int g = resident_groups(k_rowc_inv_p<N, NT>, NT, cache);
+  if (g <= 0) return hipErrorInvalidDevice;
+  const int nrows = Ky * nl;
+  hipLaunchKernelGGL((k_rowc_inv_p<N, NT>), dim3(std::min(g, nrows)), dim3(NT), 0, s, grid, T, tw, Ky, l0, nrows);
+  return hipGetLastError();
 }
 template <int N>
 hipError_t rowc_fwd_n(const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowc_fwd<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, T, grid,
-                     tw, Ky, l0);
-  return hipGetLastError();
+  return rowc_fwd_nt<N, rowc_threads<N>()>(T, grid, tw, Ky, l0, nl, s);
 }
+// The inverse holds a whole grid row (16 bytes per element pair) in flight:
+// long rows take half the threads, each with twice the registers (8192
+// points: 2.83 ms against 3.11 ms with 1024 threads, which spill the prefetch;
+// the forward is faster with 1024, 2.76 against 2.85 ms).
 template <int N>
 hipError_t rowc_inv_n(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
-  hipLaunchKernelGGL((k_rowc_inv<N, rowc_threads<N>()>), dim3(Ky, nl), dim3(rowc_threads<N>()), 0, s, grid,
-                     T, tw, Ky, l0);
-  return hipGetLastError();
+  constexpr int NT = N >= 2048 ? rowc_threads<N>() / 2 : rowc_threads<N>();
+  return rowc_inv_nt<N, NT>(grid, T, tw, Ky, l0, nl, s);
 }
 
 #define PHI_FFT_SIZES(X)                                                                              \
@@ -2587,12 +2748,23 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 }
 
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
-                        int Ky, int Kx, int T, int halo, int l0, int nl, const double* sigma, const double* scale,
-                        hipStream_t s) {
+                        const int32_t* live, int live0, int n_live, int Ky, int Kx, int T, int halo, int l0, int nl,
+                        const double* sigma, const double* scale, hipStream_t s) {
   const int tiles = (Ky / T) * (Kx / T);
-  hipLaunchKernelGGL(k_merge, dim3(tiles, nl), dim3(256), 0, s, grid, partials, tile_ptr, entries, Ky, Kx, T, halo,
+  if (live && n_live <= 0) return hipSuccess;
+  const dim3 g = live ? dim3(n_live) : dim3(tiles, nl);
+  hipLaunchKernelGGL(k_merge, g, dim3(256), 0, s, grid, partials, tile_ptr, entries, live, live0, Ky, Kx, T, halo,
                      l0, sigma, scale);
   return hipGetLastError();
+}
+
+bool fft_inverse_reads_grid_only(int Ky, int Nx) {
+  switch (Ky) {
+    case 3072: case 4096: case 5120: case 6144: case 8192:
+      return fft_image_first(Ky, Nx);
+    default:
+      return true;
+  }
 }
 
 hipError_t launch_finalize(const double* item_norms, const BlockInfo* blocks, double* block_part, const double* eps,

@@ -41,6 +41,10 @@ struct WorkList {
   std::vector<int32_t> tile_ptr;
   std::vector<TileEntry> entries;
   std::vector<int32_t> chan_item0;          // [L + 1]
+  // tiles the merge writes (some partial covers them), by channel, as
+  // channel-major tile indices; channel l's are [chan_live0[l], chan_live0[l + 1])
+  std::vector<int32_t> live;
+  std::vector<int32_t> chan_live0;          // [L + 1]
   // the items again, by pitch (largest first), for launches whose LDS is
   // sized per pitch; runs of equal pitch as (pitch, first, end)
   std::vector<Item> items_by_pitch;
@@ -84,7 +88,11 @@ struct phi_plan_s {
   size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_items_p = 0, off_binfo = 0,
          off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
-         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0;
+         off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0,
+         off_grid_a = 0, off_live = 0;
+  // the adjoint's grid is a region of its own, kept zero outside the tiles the
+  // merge writes (sparse merge), or the forward grid (every tile written)
+  bool sparse_merge = false;
   char* ws = nullptr;
   bool bound = false;
   std::vector<char> g_loaded;

@@ -27,7 +27,10 @@ def _say(*a):
 SHAPES = [(1536, 16), (2048, 16), (2560, 16), (3072, 16), (4096, 16), (4096, 32),
           # long rows: Kx = 3072 (radix 3), 4096, 5120 (radix 5, the 1536 x 2560
           # image's rows), 6144 (radix 3), 8192
-          (16, 1536), (16, 2048), (16, 2560), (16, 3072), (16, 4096)]
+          (16, 1536), (16, 2048), (16, 2560), (16, 3072), (16, 4096),
+          # long columns and long rows together (the image-first order with
+          # the persistent row passes): Kx = 3072, 5120, 6144, 8192
+          (1536, 1536), (1536, 2560), (2048, 3072), (2048, 4096)]
 
 
 @pytest.mark.parametrize("ny,nx", SHAPES)
