@@ -977,10 +977,24 @@ struct TapLayout {
 #define PHI_SCATTER_DEPTH_REGS 16
 #endif
 // The one-pass dual step runs few waves per SIMD (its LDS holds a tile and
-// an accumulator per wave) and has registers to spare: it keeps more taps in
-// flight.
+// an accumulator per wave) and keeps more taps in flight, except for plans
+// whose windows all take one 64-tap step (S <= 8): there registers set the
+// occupancy, and a shallower ring with a smaller prefetch of the next item's
+// region (512 cells: a 16-cell tile with 7 x 7 windows) runs 6 waves per
+// SIMD instead of 4 (16 x 4096^2 workload: 14.80 -> 12.68 ms; depth 4: 12.66,
+// 2: 13.31; the deeper ring stays for larger windows, 4.85 against 4.93 ms on
+// the 1024^2 workload with windows up to 17 x 17).
+#ifndef PHI_FUSED_PREFETCH_CELLS
+#define PHI_FUSED_PREFETCH_CELLS 1024
+#endif
 #ifndef PHI_FUSED_DEPTH_REGS
 #define PHI_FUSED_DEPTH_REGS 16
+#endif
+#ifndef PHI_FUSED_PREFETCH_CELLS_S8
+#define PHI_FUSED_PREFETCH_CELLS_S8 512
+#endif
+#ifndef PHI_FUSED_DEPTH_REGS_S8
+#define PHI_FUSED_DEPTH_REGS_S8 8
 #endif
 template <int GP, int NK, int REGS>
 struct Depth {
@@ -1274,7 +1288,9 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
   // trip.  Item descriptors come two items ahead as one dword per lane,
   // read with readlane, so no scalar load is waited for either.  Regions
   // beyond kPre cells per thread (pitch above 32) are copied at the start.
-  constexpr int kPre = MODE == 2 ? 1024 / kThreads : 1;
+  constexpr int kPre =
+      MODE == 2 ? (NKM == 1 ? PHI_FUSED_PREFETCH_CELLS_S8 : PHI_FUSED_PREFETCH_CELLS) / kThreads : 1;
+  constexpr int kFusedRegs = NKM == 1 ? PHI_FUSED_DEPTH_REGS_S8 : PHI_FUSED_DEPTH_REGS;
   constexpr int kWords = (int)(sizeof(Item) / 4);
   const int G = gridDim.x;
   auto cell = [&](int chan, int ty0, int tx0, int P, int e) {  // cell e of a region (rows ty0.., wrapped)
@@ -1370,7 +1386,7 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather(GArgs a, float2* _
 #define PHI_G_CASE(K)                                                                                  \
   case K:                                                                                              \
     if constexpr (K <= NKM)                                                                            \
-      wtap = gather_item<GP, MODE, K, Depth<GP, K, MODE == 2 ? PHI_FUSED_DEPTH_REGS : PHI_GATHER_DEPTH_REGS>::value>( \
+      wtap = gather_item<GP, MODE, K, Depth<GP, K, MODE == 2 ? kFusedRegs : PHI_GATHER_DEPTH_REGS>::value>( \
           a, item, r0, r1, wtap, vis, yv, rho2, res2, tile, ab);                                      \
     break;
         PHI_G_CASE(1)
