@@ -212,21 +212,20 @@ __device__ __forceinline__ int lds_i(int i) {
   return PAD ? i + (i >> 4) : i;
 }
 
-// tw holds the twiddles exp(-2 pi i m / (N TS)); a sub-transform of length N
-// reads every TS-th one.  PAD: buf is addressed through lds_i.  REG: the
-// twiddles come from tab, an LDS table of the pass's base twiddles
-// w = exp(-+2 pi i k / (NS R)), k < NS (tw_table), as w^r by squarings and
-// one product per odd r (a few ulp from the table's values), so the pass
-// issues no global load.
-// tid: the thread's index (threadIdx.x; a loop over transforms passes a copy
-// the compiler cannot see through, so the LDS addresses are formed in the
-// loop instead of being hoisted out of it and held in registers).
-template <int N, int W, int NT, bool INV, int R, int NS, int TS = 1, bool PAD = false, bool REG = false>
-__device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__ tw, const float2* tab, int tid) {
+// The pass twiddles come from tab, an LDS table of each pass's base
+// twiddles w = exp(-+2 pi i k / (NS R)), k < NS (tw_table), as w^r by
+// squarings and one product per odd r (a few ulp from exact values), so no
+// pass issues a global load (a kernel that keeps loads of its next
+// transform in flight would wait for them at such a load: vmcnt is in
+// order).  PAD: buf is addressed through lds_i.  tid: the thread's index
+// (threadIdx.x; a loop over transforms passes a copy the compiler cannot see
+// through, so the LDS addresses are formed in the loop instead of being
+// hoisted out of it and held in registers).
+template <int N, int W, int NT, bool INV, int R, int NS, bool PAD>
+__device__ __forceinline__ void fft_pass(float2* buf, const float2* tab, int tid) {
   constexpr int STRIDE = N / R;
   constexpr int NB = STRIDE * W;
   constexpr int BPT = (NB + NT - 1) / NT;
-  constexpr int TWS = N / (NS * R);
   float2 v[BPT][R];
 #pragma unroll
   for (int q = 0; q < BPT; ++q) {
@@ -235,7 +234,7 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
       const int c = j % W, b = j / W;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = buf[lds_i<PAD>((b + r * STRIDE) * W + c)];
-      if constexpr (NS > 1 && REG) {
+      if constexpr (NS > 1) {
         float2 w[R];
         w[1] = tab[b % NS];
         if (INV) w[1].y = -w[1].y;
@@ -243,14 +242,6 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
         for (int r = 2; r < R; ++r) w[r] = (r % 2 == 0) ? cmul(w[r / 2], w[r / 2]) : cmul(w[r - 1], w[1]);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], w[r]);
-      } else if constexpr (NS > 1) {
-        const int k = b % NS;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          float2 w = tw[k * TWS * r * TS];
-          if (INV) w.y = -w.y;
-          v[q][r] = cmul(v[q][r], w);
-        }
       }
     }
   }
@@ -270,21 +261,19 @@ __device__ __forceinline__ void fft_pass(float2* buf, const float2* __restrict__
   __syncthreads();
 }
 
-template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false, bool REG = false>
-__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw, const float2* tab, int tid) {
+template <int N, int W, int NT, bool INV, bool PAD = false, int NS = 1>
+__device__ __forceinline__ void fft_run(float2* buf, const float2* tab, int tid) {
   if constexpr (NS < N) {
     constexpr int R = pick_radix(N / NS);
-    fft_pass<N, W, NT, INV, R, NS, TS, PAD, REG>(buf, tw, tab, tid);
-    fft_run<N, W, NT, INV, NS * R, TS, PAD, REG>(buf, tw, REG && NS > 1 ? tab + NS : tab, tid);
+    fft_pass<N, W, NT, INV, R, NS, PAD>(buf, tab, tid);
+    fft_run<N, W, NT, INV, PAD, NS * R>(buf, NS > 1 ? tab + NS : tab, tid);
   }
 }
-template <int N, int W, int NT, bool INV, int NS, int TS = 1, bool PAD = false>
-__device__ __forceinline__ void fft_run(float2* buf, const float2* __restrict__ tw) {
-  fft_run<N, W, NT, INV, NS, TS, PAD, false>(buf, tw, nullptr, (int)threadIdx.x);
-}
 
-// Base twiddle table of fft_run<..., REG = true>: NS entries per twiddled
-// pass, tw_table_size in all.
+// Base twiddle table of fft_run: NS entries per twiddled pass,
+// tw_table_size in all; tab[k] of the pass of span NS is tw[k N / (NS R) TS]
+// for a table tw of exp(-2 pi i m / (N TS)) (a transform of length N reads
+// every TS-th entry of a longer transform's table).
 constexpr int tw_table_size(int N) {
   int s = 0;
   for (int NS = 1; NS < N;) {
@@ -292,6 +281,10 @@ constexpr int tw_table_size(int N) {
     NS *= pick_radix(N / NS);
   }
   return s;
+}
+template <int N>
+constexpr int tw_tab_len() {
+  return tw_table_size(N) > 0 ? tw_table_size(N) : 1;
 }
 template <int N, int NT, int NS, int TS>
 __device__ __forceinline__ void tw_table(float2* tab, const float2* __restrict__ tw) {
@@ -318,6 +311,8 @@ __global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, 
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
   constexpr int M = N / 2;
   __shared__ float2 buf[M + M / 16];
+  __shared__ float2 tab[tw_tab_len<M>()];
+  tw_table<M, NT, 1, 2>(tab, tw);
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
@@ -327,7 +322,7 @@ __global__ __launch_bounds__(NT) void k_rowfft_fwd(const float* __restrict__ x, 
   };
   for (int m = threadIdx.x; m < M; m += NT) buf[lds_i<true>(m)] = make_float2(sample(2 * m), sample(2 * m + 1));
   __syncthreads();
-  fft_run<M, 1, NT, false, 1, 2, true>(buf, tw);
+  fft_run<M, 1, NT, false, true>(buf, tab, threadIdx.x);
   float2* out = half + ((size_t)l * Ny + p) * N;
   for (int kk = threadIdx.x; kk < M; kk += NT) {
     const float2 a = buf[lds_i<true>(kk)], b = buf[lds_i<true>(kk == 0 ? 0 : M - kk)];
@@ -351,6 +346,8 @@ __global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ ha
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0) {
   constexpr int M = N / 2;
   __shared__ float2 buf[M + M / 16];
+  __shared__ float2 tab[tw_tab_len<M>()];
+  tw_table<M, NT, 1, 2>(tab, tw);
   const int p = blockIdx.x, l = l0 + blockIdx.y;
   const float2* in = half + ((size_t)l * Ny + p) * N;
   auto herm = [&](int k) {  // Hs[k]
@@ -366,7 +363,7 @@ __global__ __launch_bounds__(NT) void k_rowfft_inv(const float2* __restrict__ ha
     buf[lds_i<true>(kk)] = make_float2(fe.x - fo.y, fe.y + fo.x);  // Fe + i Fo
   }
   __syncthreads();
-  fft_run<M, 1, NT, true, 1, 2, true>(buf, tw);
+  fft_run<M, 1, NT, true, true>(buf, tab, threadIdx.x);
   float* xr = x + ((size_t)l * Ny + p) * Nx;
   const float syp = sy[p];
   for (int q = threadIdx.x; q < Nx; q += NT) {
@@ -383,6 +380,8 @@ template <int N, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft_fwd(const float2* __restrict__ half, float2* __restrict__ grid,
                                                    const float2* __restrict__ tw, int Ny, int Kx, int l0) {
   __shared__ float2 buf[N * W];
+  __shared__ float2 tab[tw_tab_len<N>()];
+  tw_table<N, NT, 1, 1>(tab, tw);
   const int np = Kx / W;
   const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
   const float2* in = half + (size_t)l * Ny * Kx;
@@ -392,7 +391,7 @@ __global__ __launch_bounds__(NT) void k_colfft_fwd(const float2* __restrict__ ha
     buf[e] = (p >= 0 && p < Ny) ? in[(size_t)p * Kx + c0 + c] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_run<N, W, NT, false, 1>(buf, tw);
+  fft_run<N, W, NT, false, false>(buf, tab, threadIdx.x);
   float2* out = grid + (size_t)l * N * Kx;
   for (int e = threadIdx.x; e < N * W; e += NT) {
     const int k = e / W, c = e % W;
@@ -406,6 +405,8 @@ template <int N, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ grid, float2* __restrict__ half,
                                                    const float2* __restrict__ tw, int Ny, int Kx, int l0) {
   __shared__ float2 buf[N * W];
+  __shared__ float2 tab[tw_tab_len<N>()];
+  tw_table<N, NT, 1, 1>(tab, tw);
   const int np = Kx / W;
   const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
   const float2* in = grid + (size_t)l * N * Kx;
@@ -414,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
     buf[e] = in[(size_t)k * Kx + c0 + c];
   }
   __syncthreads();
-  fft_run<N, W, NT, true, 1>(buf, tw);
+  fft_run<N, W, NT, true, false>(buf, tab, threadIdx.x);
   float2* out = half + (size_t)l * Ny * Kx;
   for (int e = threadIdx.x; e < N * W; e += NT) {
     const int k = e / W, c = e % W;
@@ -435,10 +436,18 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__ half, float2* __restrict__ grid,
                                                       const float2* __restrict__ tw, int Ny, int Kx, int l0) {
-  constexpr int N = N1 * N2;
+  constexpr int N = N1 * N2, PER = (N2 * W + NT - 1) / NT;
   __shared__ float2 buf[N2 * W];
+  __shared__ float2 tab[tw_tab_len<N2>()];
+  tw_table<N2, NT, 1, N1>(tab, tw);
   const int np = Kx / W;
   const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  float2 wst[PER];  // store twiddles w_N^(n1 k2), loaded with the data
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    wst[i] = tw[e < N2 * W ? n1 * (e / W) : 0];
+  }
   const float2* in = half + (size_t)l * Ny * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
@@ -446,37 +455,52 @@ __global__ __launch_bounds__(NT) void k_colfft2_fwd_a(const float2* __restrict__
     buf[e] = (p >= 0 && p < Ny) ? in[(size_t)p * Kx + c0 + c] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_run<N2, W, NT, false, 1, N1>(buf, tw);
+  fft_run<N2, W, NT, false, false>(buf, tab, threadIdx.x);
   float2* out = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
-  for (int e = threadIdx.x; e < N2 * W; e += NT) {
-    const int k2 = e / W, c = e % W;
-    out[(size_t)k2 * Kx + c0 + c] = cmul(buf[e], tw[n1 * k2]);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N2 * W) {
+      const int k2 = e / W, c = e % W;
+      out[(size_t)k2 * Kx + c0 + c] = cmul(buf[e], wst[i]);
+    }
   }
 }
 
 template <int N1, int N2, int W, int NT, bool INV>
 __global__ __launch_bounds__(NT) void k_colfft2_b(float2* __restrict__ grid, const float2* __restrict__ tw, int Kx,
                                                   int l0) {
-  constexpr int N = N1 * N2;
+  constexpr int N = N1 * N2, PER = (N1 * W + NT - 1) / NT;
   __shared__ float2 buf[N1 * W];
+  __shared__ float2 tab[tw_tab_len<N1>()];
+  tw_table<N1, NT, 1, N2>(tab, tw);
   const int np = Kx / W;
   const int k2 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
+  float2 wst[PER];  // inverse: conj(w_N^(n1 k2)), loaded with the data
+  if (INV) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = threadIdx.x + i * NT;
+      wst[i] = tw[e < N1 * W ? (e / W) * k2 : 0];
+      wst[i].y = -wst[i].y;
+    }
+  }
   float2* g = grid + (size_t)l * N * Kx + (size_t)k2 * Kx;
   for (int e = threadIdx.x; e < N1 * W; e += NT) {
     const int j = e / W, c = e % W;
     buf[e] = g[(size_t)N2 * j * Kx + c0 + c];
   }
   __syncthreads();
-  fft_run<N1, W, NT, INV, 1, N2>(buf, tw);
-  for (int e = threadIdx.x; e < N1 * W; e += NT) {
-    const int j = e / W, c = e % W;
-    float2 v = buf[e];
-    if (INV) {  // j = n1: apply conj(w_N^(n1 k2)) before the pass along k2
-      float2 w = tw[j * k2];
-      w.y = -w.y;
-      v = cmul(v, w);
+  fft_run<N1, W, NT, INV, false>(buf, tab, threadIdx.x);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W) {
+      const int j = e / W, c = e % W;
+      float2 v = buf[e];
+      if (INV) v = cmul(v, wst[i]);  // j = n1: conj(w_N^(n1 k2)) before the pass along k2
+      g[(size_t)N2 * j * Kx + c0 + c] = v;
     }
-    g[(size_t)N2 * j * Kx + c0 + c] = v;
   }
 }
 
@@ -485,6 +509,8 @@ __global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__
                                                       const float2* __restrict__ tw, int Ny, int Kx, int l0) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
+  __shared__ float2 tab[tw_tab_len<N2>()];
+  tw_table<N2, NT, 1, N1>(tab, tw);
   const int np = Kx / W;
   const int n1 = blockIdx.x / np, c0 = xcd_remap(blockIdx.x % np, np) * W, l = l0 + blockIdx.y;
   const float2* in = grid + (size_t)l * N * Kx + (size_t)N2 * n1 * Kx;
@@ -493,7 +519,7 @@ __global__ __launch_bounds__(NT) void k_colfft2_inv_a(const float2* __restrict__
     buf[e] = in[(size_t)k2 * Kx + c0 + c];
   }
   __syncthreads();
-  fft_run<N2, W, NT, true, 1, N1>(buf, tw);
+  fft_run<N2, W, NT, true, false>(buf, tab, threadIdx.x);
   float2* out = half + (size_t)l * Ny * Kx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
@@ -525,10 +551,18 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_a(const float* __restrict__ x, 
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0,
                                                    size_t zs) {
-  constexpr int N = N1 * N2;
+  constexpr int N = N1 * N2, PER = (N2 * W + NT - 1) / NT;
   __shared__ float2 buf[N2 * W];
+  __shared__ float2 tab[tw_tab_len<N2>()];
+  tw_table<N2, NT, 1, N1>(tab, tw);
   const int Nh = Nx / 2, npc = Nh / W;
   const int n1 = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
+  float2 wst[PER];  // store twiddles w_N^(n1 k2), loaded with the data
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    wst[i] = tw[e < N2 * W ? n1 * (e / W) : 0];
+  }
   const float* xi = x + (size_t)l * Ny * Nx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
@@ -543,11 +577,15 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_a(const float* __restrict__ x, 
     buf[e] = v;
   }
   __syncthreads();
-  fft_run<N2, W, NT, false, 1, N1>(buf, tw);
+  fft_run<N2, W, NT, false, false>(buf, tab, threadIdx.x);
   float2* out = zp + (size_t)l * zs + (size_t)N2 * n1 * Nh;
-  for (int e = threadIdx.x; e < N2 * W; e += NT) {
-    const int k2 = e / W, c = e % W;
-    out[(size_t)k2 * Nh + c0 + c] = cmul(buf[e], tw[n1 * k2]);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N2 * W) {
+      const int k2 = e / W, c = e % W;
+      out[(size_t)k2 * Nh + c0 + c] = cmul(buf[e], wst[i]);
+    }
   }
 }
 
@@ -567,6 +605,8 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp
                                                    const float2* __restrict__ tw, int Nx, int l0, size_t zs) {
   constexpr int N = N1 * N2, W2 = 2 * W;
   __shared__ float2 buf[N1 * W2];  // (k1, col): col < W group a, >= W group b
+  __shared__ float2 tab[tw_tab_len<N1>()];
+  tw_table<N1, NT, 1, N2>(tab, tw);
   const int Nh = Nx / 2, npc = Nh / W;
   const int g = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
   const int k2a = g, k2b = (N2 - g) % N2;
@@ -576,7 +616,7 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp
     buf[e] = in[(size_t)(N2 * j + k2) * Nh + c0 + c];
   }
   __syncthreads();
-  fft_run<N1, W2, NT, false, 1, N2>(buf, tw);
+  fft_run<N1, W2, NT, false, false>(buf, tab, threadIdx.x);
   float4* out = reinterpret_cast<float4*>(T + (size_t)l * N * Nx);
   const bool two = k2b != k2a;
   for (int e = threadIdx.x; e < N1 * W2; e += NT) {
@@ -604,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp
 //
 // Both are persistent: a work-group loops over rows r = blockIdx.x +
 // i gridDim.x of the nl Ky rows, with its pass twiddles in an LDS table
-// (fft_run<REG>), and loads row r + gridDim.x into registers before it
+// (fft_run), and loads row r + gridDim.x into registers before it
 // transforms row r, so the loads of one row overlap the LDS passes and the
 // stores of the other.  w^m of the load (w^-n of the store) is w^tid times
 // a uniform table entry (the inverse takes w^tid from an LDS table of the 64
@@ -661,7 +701,7 @@ __global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_fwd_p(const 
     }
     if (r + (int)gridDim.x < nrows) load(r + gridDim.x);
     __syncthreads();
-    fft_run<M, 2, NT, false, 1, 2, true, true>(buf, tw, tab, tl);
+    fft_run<M, 2, NT, false, true>(buf, tab, tl);
     const int l = l0 + r / Ky, k = r % Ky;
     float4* out = reinterpret_cast<float4*>(grid + ((size_t)l * Ky + k) * N);
     for (int i = tl; i < M; i += NT) {
@@ -672,8 +712,14 @@ __global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_fwd_p(const 
   }
 }
 
+// (6144-point rows at half the threads hold 8 prefetched elements per thread
+// through radix-3 passes: 3 waves per SIMD, not the 4 the LDS would allow.)
 template <int N, int NT>
-__global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_inv_p(const float2* __restrict__ grid,
+constexpr int rowc_inv_waves() {
+  return N == 6144 && rowc_waves<N, NT>() > 3 ? 3 : rowc_waves<N, NT>();
+}
+template <int N, int NT>
+__global__ __launch_bounds__(NT, (rowc_inv_waves<N, NT>())) void k_rowc_inv_p(const float2* __restrict__ grid,
                                                                    float2* __restrict__ T,
                                                                    const float2* __restrict__ tw, int Ky, int l0,
                                                                    int nrows) {
@@ -710,7 +756,7 @@ __global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_inv_p(const 
     }
     if (r + (int)gridDim.x < nrows) load(r + gridDim.x);
     __syncthreads();
-    fft_run<M, 2, NT, true, 1, 2, true, true>(buf, tw, tab, tl);
+    fft_run<M, 2, NT, true, true>(buf, tab, tl);
     const int l = l0 + r / Ky, k = r % Ky;
     float2* t = T + ((size_t)l * Ky + k) * Nx;
     // w^-tid = conj(w^lane w^wave_base): an LDS entry and a uniform (scalar) load
@@ -741,20 +787,28 @@ __global__ __launch_bounds__(NT, (rowc_waves<N, NT>())) void k_rowc_inv_p(const 
 template <int N1, int N2, int W, int NT>
 __global__ __launch_bounds__(NT) void k_colr_inv_b(const float2* __restrict__ T, float2* __restrict__ zp,
                                                    const float2* __restrict__ tw, int Nx, int l0, size_t zs) {
-  constexpr int N = N1 * N2, W2 = 2 * W;
+  constexpr int N = N1 * N2, W2 = 2 * W, PER = (N1 * W2 + NT - 1) / NT;
   __shared__ float4 raw[N1 * W2];  // (k1, col): the two real columns' T' values
+  __shared__ float2 tab[tw_tab_len<N1>()];
+  tw_table<N1, NT, 1, N2>(tab, tw);
   float2* buf = reinterpret_cast<float2*>(raw);  // packed values, (k1, col), after the split
   const int Nh = Nx / 2, npc = Nh / W;
   const int g = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
   const int k2a = g, k2b = (N2 - g) % N2;
   const bool two = k2b != k2a;
+  float2 wst[PER];  // store twiddles conj(w_N^(n1 k2)), loaded with the data
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    wst[i] = tw[e < N1 * W2 ? (e / W2) * ((e % W2) / W ? k2b : k2a) : 0];
+    wst[i].y = -wst[i].y;
+  }
   const float4* in = reinterpret_cast<const float4*>(T + (size_t)l * N * Nx);
   for (int e = threadIdx.x; e < N1 * W2; e += NT) {
     const int j = e / W2, col = e % W2, c = col % W, k2 = col < W ? k2a : k2b;
     raw[e] = in[((size_t)(k2 + N2 * j) * Nx) / 2 + c0 + c];
   }
   __syncthreads();
-  constexpr int PER = (N1 * W2 + NT - 1) / NT;
   float2 h[PER];
 #pragma unroll
   for (int i = 0; i < PER; ++i) {
@@ -775,15 +829,16 @@ __global__ __launch_bounds__(NT) void k_colr_inv_b(const float2* __restrict__ T,
     if (e < N1 * W2) buf[e] = h[i];
   }
   __syncthreads();
-  fft_run<N1, W2, NT, true, 1, N2>(buf, tw);
+  fft_run<N1, W2, NT, true, false>(buf, tab, threadIdx.x);
   float2* out = zp + (size_t)l * zs;
-  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
-    const int n1 = e / W2, col = e % W2, grp = col / W, c = col % W;
-    if (grp == 1 && !two) continue;
-    const int k2 = grp ? k2b : k2a;
-    float2 w = tw[n1 * k2];
-    w.y = -w.y;
-    out[(size_t)(k2 + N2 * n1) * Nh + c0 + c] = cmul(buf[e], w);
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W2) {
+      const int n1 = e / W2, col = e % W2, grp = col / W, c = col % W;
+      const int k2 = grp ? k2b : k2a;
+      if (grp == 0 || two) out[(size_t)(k2 + N2 * n1) * Nh + c0 + c] = cmul(buf[e], wst[i]);
+    }
   }
 }
 
@@ -797,6 +852,8 @@ __global__ __launch_bounds__(NT) void k_colr_inv_a(const float2* __restrict__ zp
                                                    size_t zs) {
   constexpr int N = N1 * N2;
   __shared__ float2 buf[N2 * W];
+  __shared__ float2 tab[tw_tab_len<N2>()];
+  tw_table<N2, NT, 1, N1>(tab, tw);
   const int Nh = Nx / 2, npc = Nh / W;
   const int n1 = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
   const float2* in = zp + (size_t)l * zs + (size_t)N2 * n1 * Nh;
@@ -805,7 +862,7 @@ __global__ __launch_bounds__(NT) void k_colr_inv_a(const float2* __restrict__ zp
     buf[e] = in[(size_t)k2 * Nh + c0 + c];
   }
   __syncthreads();
-  fft_run<N2, W, NT, true, 1, N1>(buf, tw);
+  fft_run<N2, W, NT, true, false>(buf, tab, threadIdx.x);
   float* xo = x + (size_t)l * Ny * Nx;
   for (int e = threadIdx.x; e < N2 * W; e += NT) {
     const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
