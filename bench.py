@@ -432,8 +432,9 @@ def main():
     ap.add_argument("--config", default="C5")
     ap.add_argument("--forms", default="plain_c64,batched_c64,batched_bf16,twopass_f16,batched_f16")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-workers", type=int, default=4,
-                    help="channels of the CPU baseline, one process each (capped by host memory and cores)")
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="channels of the CPU baseline, one process each; 0: every usable core (capped by host "
+                         "memory and the channel count)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="fix the tile edge (skips the autotuner)")
     ap.add_argument("--persist", type=int, default=0, help="persistent G-stage grid with --tile")
@@ -463,8 +464,11 @@ def main():
         hi = host_info()
         per_chan_gb = 2.5 * 16.0 * cfg_prob.M_total / cfg_prob.L * 49 / 1e9 + 4.0
         cap_mem = int(max(1.0, ((hi["ram_available_GB"] or 64.0) * 0.6) // per_chan_gb))
-        nw = max(1, min(args.cpu_workers, cfg_prob.L, hi["usable_cpus"] or 1, cap_mem))
+        want = args.cpu_workers if args.cpu_workers > 0 else (hi["usable_cpus"] or 1)
+        nw = max(1, min(want, cfg_prob.L, hi["usable_cpus"] or 1, cap_mem))
         cpu = CpuBaseline(args.config, cfg_prob.L, nw)
+        cpu.limits = {"requested": want, "channels": cfg_prob.L, "usable_cpus": hi["usable_cpus"],
+                      "memory": cap_mem, "GB_per_process_estimate": round(per_chan_gb, 1)}
         log("[bench] cpu baseline: %d oracle process(es) on channels %s, host %s" % (nw, cpu.chans, cpu.host))
 
     import torch
@@ -716,7 +720,10 @@ def main():
                       "oracle dual step per channel, each in its own process (numpy.fft and scipy.sparse, "
                       "single-threaded per process), started together; slowest %.1f s" % (
                           len(outs), cpu.chans, outs[0]["M"], prob.Ky, prob.Kx, tmax),
-            "host": cpu.host}
+            "host": cpu.host,
+            # processes = min of these (each holds one channel's FP64 operator;
+            # "memory": how many fit in 60% of the available RAM)
+            "worker_limits": cpu.limits}
         line["err_vs_fp64"] = {f: rel_err(g, ref) for f, g in samples.items()}
         line["err_vs_fp64"]["sample"] = "channel 0 (all its blocks): the oracle's inputs (x~ = x/2, v ~ 0.1 CN, " \
                                         "y at 30 dB) through each form's plan and launch flags"
