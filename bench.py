@@ -430,7 +430,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="C5")
-    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_bf16,twopass_f16,batched_f16")
+    ap.add_argument("--forms", default="plain_c64,batched_c64,batched_bf16,batched_kb,twopass_f16,batched_f16",
+                    help="forms to time: <plain|batched|fused|twopass>_<c64|bf16|f16|kb>; kb: taps evaluated "
+                         "in the kernels (Kaiser-Bessel windows without w-term only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0,
                     help="channels of the CPU baseline, one process each; 0: every usable core (capped by host "
@@ -485,6 +487,9 @@ def main():
     s_y, s_x = prob.deapodisation()
     M = int(len(S))
     Kc, Nc = prob.Ky * prob.Kx, prob.Ny * prob.Nx
+    if any(f.endswith("_kb") for f in forms) and not (np.all(S == 7) and all(np.all(b["h"] == 0) for b in blocks)):
+        log("[bench] %s has w-terms or other than 7 x 7 windows: no Kaiser-Bessel forms" % args.config)
+        forms = [f for f in forms if not f.endswith("_kb")]
     precs = []
     for f in forms:
         pr = f.split("_")[1]
@@ -523,7 +528,9 @@ def main():
         torch.cuda.synchronize()
         tb = time.perf_counter()
         for k, b in enumerate(blocks):
-            if device_g:   # rows computed on the device from the generator's tables
+            if prec == "kb":   # no stored G: the kernels evaluate the taps from kappa
+                p.load_kb(k, b["kappa"])
+            elif device_g:   # rows computed on the device from the generator's tables
                 p.build_g(k, torch.from_numpy(np.ascontiguousarray(b["kappa"])).to(dev),
                           torch.from_numpy(np.ascontiguousarray(b["h"])).to(dev),
                           torch.from_numpy(np.ascontiguousarray(b["a"])).to(dev), J=7)

@@ -312,7 +312,8 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
 }
 
 bool phi_plan_s::fused() const {
-  return gprec != PHI_G_KB && (flags & PHI_FUSED_GH) && fused_lds_bytes(W().max_pitch) > 0;
+  if (!(flags & PHI_FUSED_GH)) return false;
+  return gprec == PHI_G_KB ? kb_fused_lds_bytes(W().max_pitch) > 0 : fused_lds_bytes(W().max_pitch) > 0;
 }
 
 // Workspace regions of a plan from byte offset `base`; with `share`, the
@@ -586,9 +587,10 @@ phi_status phi_plan_get_info(phi_plan p, phi_info* info) {
   info->alg_bytes_gather = p->ntaps * bG + p->M * (4.0 + bV + 24.0) + p->L * 8.0 * K;
   info->alg_bytes_scatter = p->ntaps * bG + p->M * (4.0 + bV + 16.0);
   info->alg_bytes_dual_step = 2.0 * p->ntaps * bG + p->M * (48.0 + 2.0 * bV) + p->L * (48.0 * K + 8.0 * N);
-  // fused dual step: G read once; the fused pass moves the gather's bytes,
-  // then c is read and v+ written (16 B per visibility)
-  if (p->fused()) info->alg_bytes_dual_step = p->ntaps * bG + p->M * 44.0 + p->L * (48.0 * K + 8.0 * N);
+  // fused dual step: G (or the coordinates) read once; the fused pass moves
+  // the gather's bytes, then c is read and v+ written (16 B per visibility)
+  if (p->fused())
+    info->alg_bytes_dual_step = p->ntaps * bG + p->M * (44.0 + bV) + p->L * (48.0 * K + 8.0 * N);
   info->ky = p->Ky;
   info->kx = p->Kx;
   info->tile = p->W().T;
@@ -1264,7 +1266,8 @@ phi_status phi_plan_autotune(phi_plan p, void* stream, int32_t reps) {
       rc = PHI_ERR_HIP;
       break;
     }
-    const bool one_fits = p->gprec != PHI_G_KB && fused_lds_bytes(p->W().max_pitch) > 0;
+    const bool one_fits = p->gprec == PHI_G_KB ? kb_fused_lds_bytes(p->W().max_pitch) > 0
+                                               : fused_lds_bytes(p->W().max_pitch) > 0;
     for (int pb : {0, 4 * cus}) {
       p->persist = pb;
       p->flags = (pb ? (saved_flags | PHI_PERSISTENT) : (saved_flags & ~PHI_PERSISTENT)) & ~PHI_FUSED_GH;

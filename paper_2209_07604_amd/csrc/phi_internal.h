@@ -105,6 +105,8 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
 // sigma * scale is applied by the merge and by launch_vscale.  LDS bytes it
 // needs for the largest pitch; 0 if it does not fit a work-group.
 size_t fused_lds_bytes(int max_pitch);
+// LDS of the Kaiser-Bessel one-pass kernel (k_dual_kb), or 0 if it does not fit.
+size_t kb_fused_lds_bytes(int max_pitch);
 // v <- sigma_b * scale_b * v over the visibilities of items [it0, it1)
 hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sigma, const double* scale, int b0,
                          int nb, hipStream_t s);

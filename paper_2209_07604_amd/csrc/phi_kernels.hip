@@ -1842,6 +1842,131 @@ __global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__
   }
 }
 
+// One-pass dual step of the Kaiser-Bessel mode (PHI_G_KB with
+// PHI_FUSED_GH): one wave per item, with the item's grid tile and its
+// accumulator in LDS.  Per 64-visibility chunk each lane evaluates its
+// visibility's 2J taps once, forms c = v / sigma + theta Phi x - y from the
+// tile (k_gather_kb's sum), writes c and its FP64 norm terms; then the taps
+// go to an LDS table and the wave adds g theta c of each visibility, in
+// order, into the accumulator (k_scatter_kb's read-add-write of distinct
+// cells).  The partial holds G^H theta c; sigma_b * scale_b comes in v+
+// (k_vscale) and in the merge, as for stored G.
+template <int J>
+__global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vis, const float2* __restrict__ yv,
+                                                double* __restrict__ item_norms, int it0, int it1) {
+  constexpr int NKJ = (J * J + 63) / 64;
+  extern __shared__ float2 lds[];  // tile (P*P cells), then the accumulator (P*P + 64 cells)
+  __shared__ float psi[64][2 * J];
+  const int lane = threadIdx.x;
+  for (int it = it0 + blockIdx.x; it < it1; it += gridDim.x) {
+    const Item item = a.items[it];
+    const int P = item.pitch, PP = P * P;
+    float2* tile = lds;
+    float2* acc = lds + PP;
+    char* accb = reinterpret_cast<char*>(acc);
+    const float2* __restrict__ grid = a.grid + (size_t)item.chan * a.Ky * a.Kx;
+    for (int e = lane; e < PP; e += 64) {
+      const int r = e / P, c = e - (e / P) * P;
+      int gr = item.ty0 + r, gc = item.tx0 + c;
+      gr -= (gr >= a.Ky) ? a.Ky : 0;
+      gc -= (gc >= a.Kx) ? a.Kx : 0;
+      tile[e] = grid[(size_t)gr * a.Kx + gc];
+    }
+    for (int e = lane; e < PP + 64; e += 64) acc[e] = make_float2(0.f, 0.f);
+    const float th = a.theta[item.blk];
+    const float inv_sig = a.sigma ? (float)(1.0 / a.sigma[item.blk]) : 1.f;
+    // this lane's taps (t / J, t mod J) per step, as accumulator byte offsets
+    // from the window origin; lanes past the window use their spare cell
+    uint32_t off[NKJ];
+    int ti[NKJ], tj[NKJ];
+    bool on[NKJ];
+#pragma unroll
+    for (int k = 0; k < NKJ; ++k) {
+      const int t = k * 64 + lane;
+      on[k] = t < J * J;
+      ti[k] = on[k] ? t / J : 0;
+      tj[k] = on[k] ? t - (t / J) * J : 0;
+      off[k] = (uint32_t)(ti[k] * P + tj[k]) * 8u;
+    }
+    const uint32_t spare = (uint32_t)(PP + lane) * 8u;
+    double rho2 = 0.0, res2 = 0.0;
+    __syncthreads();
+    for (int c0 = item.v0; c0 < item.v1; c0 += 64) {
+      const int n = min(64, item.v1 - c0);
+      const bool live = lane < n;
+      const int v = live ? c0 + lane : c0 + n - 1;
+      const uint32_t m = a.meta[v];
+      const float2 fr = a.frac[v];
+      const float2 vv = vis[v], yy = yv[v];
+      float py[J], px[J];
+      kb_axis<J>(fr.x, a.kb_beta, a.kb_inv_i0b, py);
+      kb_axis<J>(fr.y, a.kb_beta, a.kb_inv_i0b, px);
+      const uint32_t base_b =
+          (uint32_t)(((int)(m & 8191) - item.ty0) * P + ((int)((m >> 13) & 8191) - item.tx0)) * 8u;
+      const char* t0 = reinterpret_cast<const char*>(tile) + base_b;
+      float ax = 0.f, ay = 0.f;
+#pragma unroll
+      for (int i = 0; i < J; ++i) {
+        const float2* row = reinterpret_cast<const float2*>(t0 + (size_t)i * P * 8);
+        float rx = 0.f, ry = 0.f;
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+          const float2 X = row[j];
+          rx = __builtin_fmaf(px[j], X.x, rx);
+          ry = __builtin_fmaf(px[j], X.y, ry);
+        }
+        ax = __builtin_fmaf(py[i], rx, ax);
+        ay = __builtin_fmaf(py[i], ry, ay);
+      }
+      const float sx = th * ax, sy = th * ay;
+      const float2 cc = make_float2(vv.x * inv_sig + sx - yy.x, vv.y * inv_sig + sy - yy.y);
+      if (live) {
+        vis[v] = cc;
+        const double rx = (double)sx - (double)yy.x, ry = (double)sy - (double)yy.y;
+        rho2 += (double)cc.x * (double)cc.x + (double)cc.y * (double)cc.y;
+        res2 += rx * rx + ry * ry;
+      }
+      const float avx = th * cc.x, avy = th * cc.y;
+      __syncthreads();  // the previous chunk's table reads are done
+#pragma unroll
+      for (int i = 0; i < J; ++i) {
+        psi[lane][i] = py[i];
+        psi[lane][J + i] = px[i];
+      }
+      __syncthreads();
+      for (int k = 0; k < n; ++k) {
+        const float vx = readlane_f(avx, k), vy = readlane_f(avy, k);
+        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base_b, k);
+        float2 cur[NKJ];
+        uint32_t ad[NKJ];
+        float g[NKJ];
+#pragma unroll
+        for (int q = 0; q < NKJ; ++q) {
+          g[q] = psi[k][ti[q]] * psi[k][J + tj[q]];
+          ad[q] = on[q] ? b + off[q] : spare;
+          cur[q] = *reinterpret_cast<float2*>(accb + ad[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < NKJ; ++q) {
+          cur[q].x = __builtin_fmaf(g[q], vx, cur[q].x);
+          cur[q].y = __builtin_fmaf(g[q], vy, cur[q].y);
+          *reinterpret_cast<float2*>(accb + ad[q]) = cur[q];
+        }
+      }
+    }
+    rho2 = wave_sum_d(rho2);
+    res2 = wave_sum_d(res2);
+    if (lane == 0) {
+      item_norms[2 * (int64_t)item.slot] = rho2;
+      item_norms[2 * (int64_t)item.slot + 1] = res2;
+    }
+    __syncthreads();
+    float2* out = a.partials + item.poff;
+    for (int e = lane; e < PP; e += 64) out[e] = acc[e];
+    __syncthreads();
+  }
+}
+
 // One work-group per (channel, tile): cell (r, c) of the tile is the
 // fixed-order sum of the tile partials covering it (its own tile's items and
 // those of the tiles up to `halo` tiles above/left, with wrap).  The partial
@@ -2727,6 +2852,12 @@ size_t fused_lds_bytes(int max_pitch) {
   return bytes <= 65536 ? bytes : 0;
 }
 
+size_t kb_fused_lds_bytes(int max_pitch) {
+  const size_t pp = (size_t)max_pitch * max_pitch;
+  const size_t bytes = (2 * pp + 64) * sizeof(float2);  // tile, accumulator, spare cells
+  return bytes <= 57344 ? bytes : 0;                   // with the static tap table, under 64 KiB
+}
+
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y, double* item_norms,
                          int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s) {
   const int n = it1 - it0;
@@ -2735,8 +2866,25 @@ hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const
   const size_t lds = mode == 2 ? fused_lds_bytes(max_pitch)
                                : ((size_t)max_pitch * max_pitch + 64) * sizeof(float2);  // tile, zero cell, norms
   if (lds == 0 || lds > 65536) return hipErrorInvalidValue;
+  if (gprec == 3 && mode == 2) {  // one wave per item: tile and accumulator in LDS
+    const size_t kb_lds = kb_fused_lds_bytes(max_pitch);
+    if (kb_lds == 0) return hipErrorInvalidValue;
+#define PHI_KB_D(JJ)                                                                                  \
+  case JJ:                                                                                            \
+    hipLaunchKernelGGL((k_dual_kb<JJ>), dim3(nb), dim3(64), kb_lds, s, a, vis, y, item_norms, it0, it1); \
+    return hipGetLastError();
+    switch (a.kb_J) {
+      PHI_KB_D(3)
+      PHI_KB_D(5)
+      PHI_KB_D(7)
+      PHI_KB_D(9)
+      PHI_KB_D(11)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef PHI_KB_D
+  }
   if (gprec == 3) {
-    if (mode == 2) return hipErrorInvalidValue;  // the Kaiser-Bessel mode has its own scatter
     const dim3 g(nb), b(64 * kGatherWaves);
 #define PHI_KB_G(JJ)                                                                                       \
   case JJ:                                                                                                 \

@@ -1,8 +1,9 @@
 """GPU parity of the Kaiser-Bessel mode (PHI_G_KB: G rows evaluated in the
 kernels from the visibilities' fractional grid coordinates) against the FP64
 oracle built from the generator's stored windows of the same
-direction-independent data.  The kernels evaluate psi in FP32 with a
-published polynomial I0, so the bound is the FP32 one, 1e-5."""
+direction-independent data, in the two-pass and the one-pass dual step.  The
+kernels evaluate psi in FP32 with a published polynomial I0, so the bound is
+the FP32 one, 1e-5."""
 import sys
 
 import numpy as np
@@ -62,6 +63,47 @@ def test_kb_forward_adjoint_dual(name):
     assert e <= 1e-5
     for l in range(c.prob.L):
         assert rel_l2(grad[l], grad_o[l]) <= 1e-5
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_kb_one_pass(name):
+    """The one-pass dual step of the Kaiser-Bessel mode (taps evaluated once
+    per window for c and for G^H theta c) against the FP64 oracle, and against
+    the two-pass Kaiser-Bessel step (norms summed in another order: 1e-12;
+    v+ and grad within the FP32 rounding of the late factor)."""
+    from test_gpu_parity import gpu_dual
+    import oracle
+    from paper_2209_07604_amd import FUSED_GH, GRAPH, PERSISTENT
+    _say("[kb] one pass", name)
+    c = case(name)
+    plan = c.plan(g_prec="kb")
+    nb = len(c.blocks)
+    sigma = np.linspace(0.8, 1.2, nb)
+    Vp_o, grad_o, rho_o, res_o = oracle.dual_step(c.op, {l: x.astype(np.float64) for l, x in c.Xt.items()},
+                                                  c.V, c.Y, c.eps, sigma)
+    plan.set_flags(0)
+    Vp2, grad2, rho2, res2 = gpu_dual(c, plan, c.V, c.eps, sigma)
+    outs = []
+    for flags in (FUSED_GH, FUSED_GH | PERSISTENT, FUSED_GH | GRAPH):
+        plan.set_flags(flags)
+        assert plan.info()["fused"] == 1
+        outs.append(gpu_dual(c, plan, c.V, c.eps, sigma))
+    Vp, grad, rho, res = outs[0]
+    e_v = rel_l2(np.concatenate(Vp), np.concatenate(Vp_o))
+    e_g = max(rel_l2(grad[l], grad_o[l]) for l in range(c.prob.L))
+    _say("  vs oracle: v+ %.2e grad %.2e rho %.2e; vs two passes: v+ %.2e grad %.2e rho %.2e" % (
+        e_v, e_g, rel_l2(rho, rho_o), rel_l2(np.concatenate(Vp), np.concatenate(Vp2)),
+        max(rel_l2(grad[l], grad2[l]) for l in range(c.prob.L)), rel_l2(rho, rho2)))
+    assert e_v <= 1e-5 and e_g <= 1e-5
+    assert rel_l2(rho, rho_o) <= 1e-5 and rel_l2(res, res_o) <= 1e-5
+    assert rel_l2(rho, rho2) <= 1e-12 and rel_l2(res, res2) <= 1e-12
+    assert rel_l2(np.concatenate(Vp), np.concatenate(Vp2)) <= 1e-6
+    for l in range(c.prob.L):
+        assert rel_l2(grad[l], grad2[l]) <= 1e-6
+    # persistent and graph-replayed one pass: bitwise the eager one pass
+    for o in outs[1:]:
+        assert all(np.array_equal(a, b) for a, b in zip(o[0], Vp))
+        assert np.array_equal(o[1], grad) and np.array_equal(o[2], rho) and np.array_equal(o[3], res)
 
 
 def test_kb_matches_stored_g_launch_forms():
