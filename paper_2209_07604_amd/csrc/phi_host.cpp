@@ -291,21 +291,26 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   }
   w.halo = (p->smax - 1 + T - 1) / T;
   if (w.halo < 1) w.halo = 1;
-  // live tiles: those whose merge list (their own partials and those of the
-  // tiles up to `halo` above / left, with wrap) is not empty
+  // merge regions of rk x rk tiles (2 x 2 where the tile grid allows: 16 x
+  // 4096^2 workload 4.51 -> 3.53 ms; 4 x 4: 6.27 ms); live regions: those
+  // whose merge list (the partials of their own tiles and of the tiles up to
+  // `halo` above / left, with wrap) is not empty
+  const int rk = (nty % 2 == 0 && ntx % 2 == 0 && (2 + w.halo) * (2 + w.halo) <= 25) ? 2 : 1;
+  w.merge_rk = rk;
+  const int nry = nty / rk, nrx = ntx / rk;
   w.live.clear();
   w.chan_live0.assign(p->L + 1, 0);
   for (int l = 0; l < p->L; ++l) {
-    for (int ty = 0; ty < nty; ++ty)
-      for (int tx = 0; tx < ntx; ++tx) {
+    for (int ry = 0; ry < nry; ++ry)
+      for (int rx = 0; rx < nrx; ++rx) {
         bool any = false;
-        for (int dy = 0; dy <= w.halo && !any; ++dy)
-          for (int dx = 0; dx <= w.halo && !any; ++dx) {
-            const int sty = ((ty - dy) % nty + nty) % nty, stx = ((tx - dx) % ntx + ntx) % ntx;
+        for (int dy = -w.halo; dy < rk && !any; ++dy)
+          for (int dx = -w.halo; dx < rk && !any; ++dx) {
+            const int sty = ((ry * rk + dy) % nty + nty) % nty, stx = ((rx * rk + dx) % ntx + ntx) % ntx;
             const int64_t t = ((int64_t)l * nty + sty) * ntx + stx;
             any = w.tile_ptr[t + 1] > w.tile_ptr[t];
           }
-        if (any) w.live.push_back((int32_t)(((int64_t)l * nty + ty) * ntx + tx));
+        if (any) w.live.push_back((int32_t)(((int64_t)l * nry + ry) * nrx + rx));
       }
     w.chan_live0[l + 1] = (int32_t)w.live.size();
   }
@@ -940,8 +945,8 @@ struct Runner {
     const int32_t* live = p->sparse_merge ? p->at<int32_t>(p->off_live) : nullptr;
     const int lb = live ? w.chan_live0[l0] : 0, ln = live ? w.chan_live0[l1] - w.chan_live0[l0] : 0;
     return launch_merge(p->at<float2>(p->off_grid_a), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
-                        p->at<TileEntry>(p->off_ent), live, lb, ln, p->Ky, p->Kx, w.T, w.halo, l0, l1 - l0, msig,
-                        mscale, s);
+                        p->at<TileEntry>(p->off_ent), live, lb, ln, p->Ky, p->Kx, w.T, w.halo, w.merge_rk, l0,
+                        l1 - l0, msig, mscale, s);
   }
   // msig / mscale: per-block merge factors after the fused dual step (null: 1)
   void adj_fft(float* x, int l0, int l1, const double* msig = nullptr, const double* mscale = nullptr) {

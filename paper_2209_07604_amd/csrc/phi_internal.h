@@ -114,12 +114,13 @@ hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sig
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
                           int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
 // sigma/scale: per-block factors sigma_b * scale_b applied to each item's
-// partial (entry .blk), or scale null for factor 1.  live: the tiles to
-// write, live[live0 .. live0 + n_live) (channel-major tile indices), or null
-// for every tile of channels [l0, l0 + nl).
+// partial (entry .blk), or scale null for factor 1.  A work-group merges a
+// region of rk x rk tiles (rk 1 or 2).  live: the regions to write,
+// live[live0 .. live0 + n_live) (channel-major region indices), or null for
+// every region of channels [l0, l0 + nl).
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,
                         const TileEntry* entries, const int32_t* live, int live0, int n_live, int Ky, int Kx, int T,
-                        int halo, int l0, int nl, const double* sigma, const double* scale, hipStream_t s);
+                        int halo, int rk, int l0, int nl, const double* sigma, const double* scale, hipStream_t s);
 // True where the inverse 2-D transform leaves its input grid unchanged (it
 // runs in place on it for rows-first grids whose columns take two passes).
 bool fft_inverse_reads_grid_only(int Ky, int Nx);

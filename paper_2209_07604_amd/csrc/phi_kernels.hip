@@ -1967,11 +1967,16 @@ __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vi
   }
 }
 
-// One work-group per (channel, tile): cell (r, c) of the tile is the
-// fixed-order sum of the tile partials covering it (its own tile's items and
-// those of the tiles up to `halo` tiles above/left, with wrap).  The partial
-// list is staged in LDS once per tile; reads of a partial row are coalesced.
+// One work-group per (channel, region): a region is rk x rk tiles of edge T
+// (rk = 1 or 2), and cell (r, c) of it is the fixed-order sum of the tile
+// partials covering it: those of the tiles up to `halo` tiles above / left
+// of the region and of its own tiles (with wrap), source tile by source
+// tile, items in tile order.  A 2 x 2 region reads each of its own tiles'
+// partials once, where four single-tile work-groups would each read the part
+// that covers them.  The partial list is staged in LDS once per region;
+// reads of a partial row are coalesced.
 constexpr int kMergeList = 256;
+constexpr int kMergeSrc = 25;  // (rk + halo)^2 source tiles at most
 // Factor of an item's partial in the merge: sigma_b * scale_b after the fused
 // dual step (its partials hold G^H theta c), else 1 (exact: fma(1, v, s) = s + v).
 __device__ __forceinline__ float merge_factor(const double* sigma, const double* scale, int blk) {
@@ -1981,28 +1986,33 @@ __device__ __forceinline__ float merge_factor(const double* sigma, const double*
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
                                                const TileEntry* __restrict__ ent, const int32_t* __restrict__ live,
-                                               int live0, int Ky, int Kx, int T, int halo, int l0,
+                                               int live0, int Ky, int Kx, int T, int halo, int rk, int l0,
                                                const double* __restrict__ sigma, const double* __restrict__ scale) {
   __shared__ int64_t s_off[kMergeList];
   __shared__ int32_t s_pitch[kMergeList];
   __shared__ float s_fac[kMergeList];
   __shared__ int32_t s_oy[kMergeList], s_ox[kMergeList];
-  __shared__ int s_beg[16], s_pre[17];
-  const int nty = Ky / T, ntx = Kx / T;
-  int l = l0 + blockIdx.y, tile_i = blockIdx.x;
+  __shared__ int s_beg[kMergeSrc], s_pre[kMergeSrc + 1];
+  const int nty = Ky / T, ntx = Kx / T, R = rk * T, nry = Ky / R, nrx = Kx / R;
+  int l = l0 + blockIdx.y, reg = blockIdx.x;
   if (live) {
     const int t = live[live0 + blockIdx.x];
-    l = t / (nty * ntx);
-    tile_i = t % (nty * ntx);
+    l = t / (nry * nrx);
+    reg = t % (nry * nrx);
   }
-  const int ty = tile_i / ntx, tx = tile_i % ntx;
-  const int hw = halo + 1, nsrc = hw * hw;   // halo <= 3: at most 16 source tiles
+  const int ry = reg / nrx, rx = reg % nrx;
+  const int sw = rk + halo, nsrc = sw * sw;   // source tile offsets dy, dx in [-halo, rk)
+  // source tile j (dy = j / sw - halo, dx = j % sw - halo) of the region
+  auto src_tile = [&](int j) {
+    int sty = ry * rk + j / sw - halo, stx = rx * rk + j % sw - halo;
+    sty += sty < 0 ? nty : 0;
+    stx += stx < 0 ? ntx : 0;
+    sty -= sty >= nty ? nty : 0;
+    stx -= stx >= ntx ? ntx : 0;
+    return ((int64_t)l * nty + sty) * ntx + stx;
+  };
   if ((int)threadIdx.x < nsrc) {
-    const int dy = threadIdx.x / hw, dx = threadIdx.x % hw;
-    int sty = ty - dy, stx = tx - dx;
-    while (sty < 0) sty += nty;
-    while (stx < 0) stx += ntx;
-    const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
+    const int64_t tile = src_tile(threadIdx.x);
     s_beg[threadIdx.x] = tile_ptr[tile];
     s_pre[threadIdx.x + 1] = tile_ptr[tile + 1] - tile_ptr[tile];
   }
@@ -2020,13 +2030,13 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
     s_off[e] = te.poff;
     s_pitch[e] = te.pitch;
     s_fac[e] = merge_factor(sigma, scale, te.blk);
-    s_oy[e] = (j / hw) * T;
-    s_ox[e] = (j % hw) * T;
+    s_oy[e] = (halo - j / sw) * T;  // partial row of region row r: r + s_oy
+    s_ox[e] = (halo - j % sw) * T;
   }
   __syncthreads();
   float2* out = grid + (int64_t)l * Ky * Kx;
-  for (int e = threadIdx.x; e < T * T; e += 256) {
-    const int r = e / T, c = e % T;
+  for (int e = threadIdx.x; e < R * R; e += 256) {
+    const int r = e / R, c = e % R;
     float sx = 0.f, sy = 0.f;
     if (n <= kMergeList) {
       // four entries at a time, loads first: an entry that does not cover
@@ -2039,7 +2049,7 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ly = r + s_oy[k + u], lx = c + s_ox[k + u], P = s_pitch[k + u];
-          const bool in = ly < P && lx < P;
+          const bool in = (unsigned)ly < (unsigned)P && (unsigned)lx < (unsigned)P;
           f[u] = in ? s_fac[k + u] : 0.f;
           v[u] = partials[s_off[k + u] + (in ? (int64_t)ly * P + lx : 0)];
         }
@@ -2051,34 +2061,28 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
       }
       for (; k < n; ++k) {
         const int ly = r + s_oy[k], lx = c + s_ox[k], P = s_pitch[k];
-        if (ly < P && lx < P) {
+        if ((unsigned)ly < (unsigned)P && (unsigned)lx < (unsigned)P) {
           const float2 v = partials[s_off[k] + (int64_t)ly * P + lx];
           sx = __builtin_fmaf(s_fac[k], v.x, sx);
           sy = __builtin_fmaf(s_fac[k], v.y, sy);
         }
       }
     } else {  // long lists: same order, read from global memory
-      for (int dy = 0; dy <= halo; ++dy) {
-        int sty = ty - dy;
-        while (sty < 0) sty += nty;
-        for (int dx = 0; dx <= halo; ++dx) {
-          int stx = tx - dx;
-          while (stx < 0) stx += ntx;
-          const int64_t tile = ((int64_t)l * nty + sty) * ntx + stx;
-          const int ly = r + dy * T, lx = c + dx * T;
-          for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
-            const TileEntry te = ent[k];
-            if (ly < te.pitch && lx < te.pitch) {
-              const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
-              const float f = merge_factor(sigma, scale, te.blk);
-              sx = __builtin_fmaf(f, v.x, sx);
-              sy = __builtin_fmaf(f, v.y, sy);
-            }
+      for (int j = 0; j < nsrc; ++j) {
+        const int64_t tile = src_tile(j);
+        const int ly = r + (halo - j / sw) * T, lx = c + (halo - j % sw) * T;
+        for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
+          const TileEntry te = ent[k];
+          if ((unsigned)ly < (unsigned)te.pitch && (unsigned)lx < (unsigned)te.pitch) {
+            const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+            const float f = merge_factor(sigma, scale, te.blk);
+            sx = __builtin_fmaf(f, v.x, sx);
+            sy = __builtin_fmaf(f, v.y, sy);
           }
         }
       }
     }
-    out[(int64_t)(ty * T + r) * Kx + tx * T + c] = make_float2(sx, sy);
+    out[(int64_t)(ry * R + r) * Kx + rx * R + c] = make_float2(sx, sy);
   }
 }
 
@@ -2969,13 +2973,15 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 }
 
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
-                        const int32_t* live, int live0, int n_live, int Ky, int Kx, int T, int halo, int l0, int nl,
-                        const double* sigma, const double* scale, hipStream_t s) {
-  const int tiles = (Ky / T) * (Kx / T);
+                        const int32_t* live, int live0, int n_live, int Ky, int Kx, int T, int halo, int rk, int l0,
+                        int nl, const double* sigma, const double* scale, hipStream_t s) {
+  if (rk < 1 || rk > 2 || (rk + halo) * (rk + halo) > kMergeSrc || Ky % (rk * T) || Kx % (rk * T))
+    return hipErrorInvalidValue;
+  const int regions = (Ky / (rk * T)) * (Kx / (rk * T));
   if (live && n_live <= 0) return hipSuccess;
-  const dim3 g = live ? dim3(n_live) : dim3(tiles, nl);
+  const dim3 g = live ? dim3(n_live) : dim3(regions, nl);
   hipLaunchKernelGGL(k_merge, g, dim3(256), 0, s, grid, partials, tile_ptr, entries, live, live0, Ky, Kx, T, halo,
-                     l0, sigma, scale);
+                     rk, l0, sigma, scale);
   return hipGetLastError();
 }
 

@@ -41,8 +41,10 @@ struct WorkList {
   std::vector<int32_t> tile_ptr;
   std::vector<TileEntry> entries;
   std::vector<int32_t> chan_item0;          // [L + 1]
-  // tiles the merge writes (some partial covers them), by channel, as
-  // channel-major tile indices; channel l's are [chan_live0[l], chan_live0[l + 1])
+  // the merge's regions (merge_rk x merge_rk tiles) that some partial
+  // covers, by channel, as channel-major region indices; channel l's are
+  // [chan_live0[l], chan_live0[l + 1])
+  int merge_rk = 1;
   std::vector<int32_t> live;
   std::vector<int32_t> chan_live0;          // [L + 1]
   // the items again, by pitch (largest first), for launches whose LDS is
