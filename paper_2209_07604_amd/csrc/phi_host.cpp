@@ -291,11 +291,12 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   }
   w.halo = (p->smax - 1 + T - 1) / T;
   if (w.halo < 1) w.halo = 1;
-  // merge regions of rk x rk tiles (2 x 2 where the tile grid allows: 16 x
-  // 4096^2 workload 4.51 -> 3.53 ms; 4 x 4: 6.27 ms); live regions: those
-  // whose merge list (the partials of their own tiles and of the tiles up to
-  // `halo` above / left, with wrap) is not empty
-  const int rk = (nty % 2 == 0 && ntx % 2 == 0 && (2 + w.halo) * (2 + w.halo) <= 25) ? 2 : 1;
+  // merge regions of rk x rk tiles, 32 cells wide where the tile grid allows
+  // (16-cell tiles on the 16 x 4096^2 workload: 4.51 -> 3.53 ms; 64-cell
+  // regions: 6.27 ms); live regions: those whose merge list (the partials of
+  // their own tiles and of the tiles up to `halo` above / left, with wrap) is
+  // not empty
+  const int rk = (T == 16 && nty % 2 == 0 && ntx % 2 == 0 && (2 + w.halo) * (2 + w.halo) <= 25) ? 2 : 1;
   w.merge_rk = rk;
   const int nry = nty / rk, nrx = ntx / rk;
   w.live.clear();

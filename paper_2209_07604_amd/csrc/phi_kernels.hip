@@ -1757,6 +1757,38 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_kb(GArgs a, float2
   }
 }
 
+// Adds g theta c of a chunk's n visibilities, in order, into a wave's LDS
+// accumulator (byte base accb): for each visibility the lanes span its J x J
+// window (tap t = q 64 + lane at byte offset off[q] from the window origin,
+// weights from the table psi; lanes past the window use their spare cell)
+// and read-add-write distinct cells.  (Taking two windows whose squares do
+// not overlap together, with one LDS round trip, measured slower: the
+// per-step overlap test costs more than the round trip it saves.)
+template <int J, int NKJ>
+__device__ __forceinline__ void kb_accumulate(char* accb, const float (*psi)[2 * J], int n, float avx, float avy,
+                                              uint32_t base_b, const uint32_t (&off)[NKJ], const int (&ti)[NKJ],
+                                              const int (&tj)[NKJ], const bool (&on)[NKJ], uint32_t spare) {
+  for (int k = 0; k < n; ++k) {
+    const float vx = readlane_f(avx, k), vy = readlane_f(avy, k);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base_b, k);
+    float2 cur[NKJ];
+    uint32_t ad[NKJ];
+    float g[NKJ];
+#pragma unroll
+    for (int q = 0; q < NKJ; ++q) {
+      g[q] = psi[k][ti[q]] * psi[k][J + tj[q]];
+      ad[q] = on[q] ? b + off[q] : spare;
+      cur[q] = *reinterpret_cast<float2*>(accb + ad[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NKJ; ++q) {
+      cur[q].x = __builtin_fmaf(g[q], vx, cur[q].x);
+      cur[q].y = __builtin_fmaf(g[q], vy, cur[q].y);
+      *reinterpret_cast<float2*>(accb + ad[q]) = cur[q];
+    }
+  }
+}
+
 // Adjoint: one wave per item owns its LDS accumulator as in k_scatter.  Per
 // 64-visibility chunk, lane l evaluates visibility l's 2J taps into an LDS
 // table; then for each visibility in order the lanes span its J x J window
@@ -1815,25 +1847,7 @@ __global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__
         psi[lane][J + i] = px[i];
       }
       __syncthreads();
-      for (int k = 0; k < n; ++k) {
-        const float vx = readlane_f(avx, k), vy = readlane_f(avy, k);
-        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base_b, k);
-        float2 cur[NKJ];
-        uint32_t ad[NKJ];
-        float g[NKJ];
-#pragma unroll
-        for (int q = 0; q < NKJ; ++q) {
-          g[q] = psi[k][ti[q]] * psi[k][J + tj[q]];
-          ad[q] = on[q] ? b + off[q] : spare;
-          cur[q] = *reinterpret_cast<float2*>(accb + ad[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < NKJ; ++q) {
-          cur[q].x = __builtin_fmaf(g[q], vx, cur[q].x);
-          cur[q].y = __builtin_fmaf(g[q], vy, cur[q].y);
-          *reinterpret_cast<float2*>(accb + ad[q]) = cur[q];
-        }
-      }
+      kb_accumulate<J, NKJ>(accb, psi, n, avx, avy, base_b, off, ti, tj, on, spare);
     }
     __syncthreads();
     float2* out = partials + item.poff;
@@ -1934,25 +1948,7 @@ __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vi
         psi[lane][J + i] = px[i];
       }
       __syncthreads();
-      for (int k = 0; k < n; ++k) {
-        const float vx = readlane_f(avx, k), vy = readlane_f(avy, k);
-        const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)base_b, k);
-        float2 cur[NKJ];
-        uint32_t ad[NKJ];
-        float g[NKJ];
-#pragma unroll
-        for (int q = 0; q < NKJ; ++q) {
-          g[q] = psi[k][ti[q]] * psi[k][J + tj[q]];
-          ad[q] = on[q] ? b + off[q] : spare;
-          cur[q] = *reinterpret_cast<float2*>(accb + ad[q]);
-        }
-#pragma unroll
-        for (int q = 0; q < NKJ; ++q) {
-          cur[q].x = __builtin_fmaf(g[q], vx, cur[q].x);
-          cur[q].y = __builtin_fmaf(g[q], vy, cur[q].y);
-          *reinterpret_cast<float2*>(accb + ad[q]) = cur[q];
-        }
-      }
+      kb_accumulate<J, NKJ>(accb, psi, n, avx, avy, base_b, off, ti, tj, on, spare);
     }
     rho2 = wave_sum_d(rho2);
     res2 = wave_sum_d(res2);
