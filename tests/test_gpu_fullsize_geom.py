@@ -11,6 +11,8 @@ against the FP64 oracle on every output (v+, grad, rho, r).
 * 1536 x 2560 images (3072 x 5120 grid: radix-3 columns, radix-5 rows), one
   channel of 3M visibilities in two blocks with w-stencils 7..17, host
   windows: complex64 G at 1e-5, FP16 G at 2e-3 against the FP64 G.
+* 2048^2 images (4096^2 grid) with w + DDE windows 7..21 in 8 uneven blocks
+  (one channel of the 64-channel workload), at the same bounds.
 """
 import sys
 
@@ -180,3 +182,57 @@ def test_c4_geometry_channel(prec, bound):
 
 
 _C4 = {}
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec,bound", [("c64", 1e-5), ("f16", 2e-3)])
+def test_c3_geometry_channel(prec, bound):
+    """Channel 9 of the 64-channel w + DDE workload at its full geometry:
+    2048^2 image (4096^2 grid, image-first transform), 8 uneven blocks
+    (1.0e4 ... 9.8e4 visibilities, 3.4e5 in all), windows 7 ... 21 (the
+    largest step class), host windows; autotuned launch form and hipGraph."""
+    import oracle
+    import synth
+    from paper_2209_07604_amd import Plan, GRAPH, FUSED_GH, PERSISTENT
+    full = synth.make_problem("C3")
+    c = 9
+    prob = synth.make_problem("C3", L=1, n_blocks=[full.n_blocks[c]], n_vis=[full.n_vis[c]], nu=full.nu[c:c + 1])
+    if "c3" not in _C3:
+        wins = []
+        for b in range(prob.n_blocks[0]):
+            blk = prob.block(0, b)
+            wins.append((blk,) + tuple(blk.windows(np.complex128)))
+        D = _channel_inputs(prob, 0, wins)
+        op = _oracle_channel(prob, 0, wins, D["theta"])
+        want = oracle.dual_step(op, D["Xt"], D["V"], D["Y"], D["eps"])
+        del op
+        _C3["c3"] = (wins, D, want)
+        _say("[geom] C3 channel oracle ready")
+    wins, D, want = _C3["c3"]
+    s_y, s_x = prob.deapodisation()
+    n_vis = [w[0].M for w in wins]
+    S = np.concatenate([w[0].S for w in wins])
+    assert S.min() == 7 and S.max() == 21 and len(wins) == 8
+    plan = Plan(prob.Ny, prob.Nx, prob.n_blocks, n_vis, np.concatenate([w[0].base for w in wins]), S, s_y, s_x,
+                np.full(len(wins), D["theta"]), g_prec=prec)
+    for k, w in enumerate(wins):
+        plan.load_g(k, w[1])
+    plan.autotune(3)
+    i = plan.info()
+    assert i["fft_image_first"] == 1
+    plan.set_flags(GRAPH | (PERSISTENT if i["persist_blocks"] else 0) | (FUSED_GH if i["fused"] else 0))
+    _say("[geom] C3", prec, plan.info())
+    xt = torch.from_numpy((0.5 * prob.image(0))[None].astype(np.float32)).cuda()
+    v = plan.to_plan(torch.from_numpy(np.concatenate(D["V"]).astype(np.complex64)).cuda())
+    y = plan.to_plan(torch.from_numpy(np.concatenate(D["Y"]).astype(np.complex64)).cuda())
+    eps = torch.from_numpy(np.asarray(D["eps"], np.float64)).cuda()
+    grad, rho, res = plan.dual_step(xt, v, y, eps)
+    vp = plan.from_plan(v).cpu().numpy()
+    torch.cuda.synchronize()
+    plan.check()
+    _check("C3 geometry channel 9, %s headline vs oracle with FP64 G" % prec,
+           (vp, grad[0].cpu().numpy().astype(np.float64), rho.cpu().numpy(), res.cpu().numpy()),
+           (want[0], want[1][0], want[2], want[3]), D["eps"], bound)
+
+
+_C3 = {}
