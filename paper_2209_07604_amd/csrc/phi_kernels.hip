@@ -2031,6 +2031,65 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
   }
   __syncthreads();
   float2* out = grid + (int64_t)l * Ky * Kx;
+  // cell (r, c) of the region from the global lists (lists beyond kMergeList)
+  auto cell_from_lists = [&](int r, int c, float& sx, float& sy) {
+    for (int j = 0; j < nsrc; ++j) {
+      const int64_t tile = src_tile(j);
+      const int ly = r + (halo - j / sw) * T, lx = c + (halo - j % sw) * T;
+      for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
+        const TileEntry te = ent[k];
+        if ((unsigned)ly < (unsigned)te.pitch && (unsigned)lx < (unsigned)te.pitch) {
+          const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
+          const float f = merge_factor(sigma, scale, te.blk);
+          sx = __builtin_fmaf(f, v.x, sx);
+          sy = __builtin_fmaf(f, v.y, sy);
+        }
+      }
+    }
+  };
+  if (R >= 32) {
+    // Regions of 32 or 64 cells: each wave takes 16 x 16 sub-squares, lane
+    // (lr, lc) the cells (r0 + 4q + lr, c0 + lc), q < 4, and passes over the
+    // entries whose partial misses the sub-square (a wave-uniform test): of
+    // the (rk + halo)^2 source tiles only those next to the sub-square reach
+    // it.  A skipped entry would have added exactly zero, so every cell's sum
+    // keeps its terms and their order.
+    const int lane = threadIdx.x & 63, lr = lane >> 4, lc = lane & 15, nsq = R / 16;
+    for (int sq = (int)(threadIdx.x >> 6); sq < nsq * nsq; sq += 4) {
+      const int r0 = (sq / nsq) * 16, c0 = (sq % nsq) * 16, c = c0 + lc;
+      float sx[4] = {0.f, 0.f, 0.f, 0.f}, sy[4] = {0.f, 0.f, 0.f, 0.f};
+      if (n <= kMergeList) {
+        for (int k = 0; k < n; ++k) {
+          const int oy = s_oy[k], ox = s_ox[k], P = s_pitch[k];
+          if (r0 + oy >= P || r0 + 15 + oy < 0 || c0 + ox >= P || c0 + 15 + ox < 0) continue;
+          const float fk = s_fac[k];
+          const int64_t off = s_off[k];
+          const int lx = c + ox;
+          const bool inx = (unsigned)lx < (unsigned)P;
+          float2 v[4];
+          float f[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {  // loads first; a cell the partial misses reads its first cell, weight 0
+            const int ly = r0 + 4 * q + lr + oy;
+            const bool in = inx && (unsigned)ly < (unsigned)P;
+            f[q] = in ? fk : 0.f;
+            v[q] = partials[off + (in ? (int64_t)ly * P + lx : 0)];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            sx[q] = __builtin_fmaf(f[q], v[q].x, sx[q]);
+            sy[q] = __builtin_fmaf(f[q], v[q].y, sy[q]);
+          }
+        }
+      } else {
+        for (int q = 0; q < 4; ++q) cell_from_lists(r0 + 4 * q + lr, c, sx[q], sy[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        out[(int64_t)(ry * R + r0 + 4 * q + lr) * Kx + rx * R + c] = make_float2(sx[q], sy[q]);
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < R * R; e += 256) {
     const int r = e / R, c = e % R;
     float sx = 0.f, sy = 0.f;
@@ -2064,19 +2123,7 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
         }
       }
     } else {  // long lists: same order, read from global memory
-      for (int j = 0; j < nsrc; ++j) {
-        const int64_t tile = src_tile(j);
-        const int ly = r + (halo - j / sw) * T, lx = c + (halo - j % sw) * T;
-        for (int k = tile_ptr[tile]; k < tile_ptr[tile + 1]; ++k) {
-          const TileEntry te = ent[k];
-          if ((unsigned)ly < (unsigned)te.pitch && (unsigned)lx < (unsigned)te.pitch) {
-            const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
-            const float f = merge_factor(sigma, scale, te.blk);
-            sx = __builtin_fmaf(f, v.x, sx);
-            sy = __builtin_fmaf(f, v.y, sy);
-          }
-        }
-      }
+      cell_from_lists(r, c, sx, sy);
     }
     out[(int64_t)(ry * R + r) * Kx + rx * R + c] = make_float2(sx, sy);
   }
