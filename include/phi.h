@@ -96,12 +96,12 @@ enum {
                            instead of one launch over all channels/blocks  */
   PHI_GRAPH = 2,        /* replay the dual step from a captured hipGraph    */
   PHI_PERSISTENT = 4,   /* G stages run as a persistent grid over work items */
-  PHI_FUSED_GH = 8,     /* dual step in one pass over G (c and G^H theta c
-                           from the same taps; sigma * scale applied to v+
-                           and in the merge) instead of a G pass and a G^H
-                           pass; used with stored G where the item's grid
-                           tile and one accumulator per wave fit a
-                           work-group's LDS (e.g. 16-cell tiles)            */
+  PHI_FUSED_GH = 8,     /* dual step in one pass over G (c and G^H c from
+                           the same taps; sigma * scale applied to v+, and
+                           times theta in the merge) instead of a G pass
+                           and a G^H pass; used with stored G where the
+                           item's grid tile and one accumulator per wave
+                           fit a work-group's LDS (e.g. 16-cell tiles)      */
   PHI_DR = 16           /* at plan creation only: also build the plan of the
                            visibility-gridding reduction (phi_dr_setup) in
                            the same workspace; stored G only, kept in

@@ -947,7 +947,7 @@ struct Runner {
     const int lb = live ? w.chan_live0[l0] : 0, ln = live ? w.chan_live0[l1] - w.chan_live0[l0] : 0;
     return launch_merge(p->at<float2>(p->off_grid_a), p->at<float2>(p->off_part), p->at<int32_t>(p->off_tptr),
                         p->at<TileEntry>(p->off_ent), live, lb, ln, p->Ky, p->Kx, w.T, w.halo, w.merge_rk, l0,
-                        l1 - l0, msig, mscale, s);
+                        l1 - l0, msig, mscale, p->at<float>(p->off_theta), s);
   }
   // msig / mscale: per-block merge factors after the fused dual step (null: 1)
   void adj_fft(float* x, int l0, int l1, const double* msig = nullptr, const double* mscale = nullptr) {
@@ -1025,8 +1025,9 @@ struct Runner {
     a.sigma = sigma;
     const int b0 = p->chan_blk0[l0], b1 = p->chan_blk0[l1];
     if (p->fused()) {
-      // c and G^H theta c in one pass over G; the per-block factor
-      // sigma * scale goes into v+ and the merge once the norms are known
+      // c and G^H c in one pass over G; once the norms are known the
+      // per-block factor sigma * scale goes into v+, and times theta into
+      // the merge
       stage(10, [&] { return gather(2, a, v, y, l0, l1); });
       stage(3, [&] {
         return launch_finalize(p->at<double>(p->off_norms), p->at<BlockInfo>(p->off_binfo),

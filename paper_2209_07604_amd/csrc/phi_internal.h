@@ -101,8 +101,9 @@ hipError_t launch_colr_inv(int Ky, const float2* T, float2* zp, float* x, const 
 hipError_t launch_gather(int gprec, int mode, const GArgs& a, float2* vis, const float2* y,
                          double* item_norms, int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
 // Fused dual step (mode 2 of the gather): c per visibility and, with the same
-// G taps, G^H theta c into per-item tile partials; the per-block factor
-// sigma * scale is applied by the merge and by launch_vscale.  LDS bytes it
+// G taps, G^H c into per-item tile partials; the per-block factors
+// sigma * scale * theta (merge) and sigma * scale (launch_vscale) come after
+// the norms.  LDS bytes it
 // needs for the largest pitch; 0 if it does not fit a work-group.
 size_t fused_lds_bytes(int max_pitch);
 // LDS of the Kaiser-Bessel one-pass kernel (k_dual_kb), or 0 if it does not fit.
@@ -113,14 +114,16 @@ hipError_t launch_vscale(const BlockInfo* blocks, float2* vis, const double* sig
 // mode: 0 adjoint (read v), 1 dual (v+ = sigma*scale*c, written back)
 hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, float2* partials,
                           int max_pitch, int it0, int it1, int grid_blocks, hipStream_t s);
-// sigma/scale: per-block factors sigma_b * scale_b applied to each item's
-// partial (entry .blk), or scale null for factor 1.  A work-group merges a
-// region of rk x rk tiles (rk 1 or 2).  live: the regions to write,
-// live[live0 .. live0 + n_live) (channel-major region indices), or null for
-// every region of channels [l0, l0 + nl).
+// sigma/scale/theta: per-block factors sigma_b * scale_b * theta_b applied to
+// each item's partial (entry .blk) after the one-pass dual step (sigma null:
+// 1), or scale null for factor 1.  A work-group merges a region of rk x rk
+// tiles (rk 1 or 2).  live: the regions to write, live[live0 .. live0 +
+// n_live) (channel-major region indices), or null for every region of
+// channels [l0, l0 + nl).
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,
                         const TileEntry* entries, const int32_t* live, int live0, int n_live, int Ky, int Kx, int T,
-                        int halo, int rk, int l0, int nl, const double* sigma, const double* scale, hipStream_t s);
+                        int halo, int rk, int l0, int nl, const double* sigma, const double* scale,
+                        const float* theta, hipStream_t s);
 // True where the inverse 2-D transform leaves its input grid unchanged (it
 // runs in place on it for rows-first grids whose columns take two passes).
 bool fft_inverse_reads_grid_only(int Ky, int Nx);

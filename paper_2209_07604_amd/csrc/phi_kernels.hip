@@ -1060,10 +1060,11 @@ struct Depth {
 };
 
 // MODE 0: y = Phi x.  MODE 1: c = v / sigma + Phi x - y with FP64 norms.
-// MODE 2: as MODE 1, and each window's c is also added as conj(g) theta c
-// into this wave's LDS accumulator (byte offset ab, pitch P, a spare cell per
-// lane behind it) with the same G taps: the dual step's G^H without reading G
-// again (the per-block factor sigma * scale comes later, in the merge).
+// MODE 2: as MODE 1, and each window's c is also added as conj(g) c into
+// this wave's LDS accumulator (byte offset ab, pitch P, a spare cell per lane
+// behind it) with the same G taps: the dual step's G^H without reading G
+// again (the per-block factor sigma * scale * theta comes later, in the
+// merge).
 template <int GP, int MODE, int NK, int D>
 __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item, int v0, int v1, int64_t tap0,
                                             float2* __restrict__ vis, const float2* __restrict__ yv,
@@ -1163,8 +1164,9 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     res.y = writelane_f(res.y, py, rel);
   };
   // MODE 2: c of a window from its sum (the same operations as the flush, so
-  // the c added here is the c written to v), then conj(g) theta c into the
-  // accumulator: read the window's cells, add, write (distinct cells)
+  // the c added here is the c written to v), then conj(g) c into the
+  // accumulator: read the window's cells, add, write (distinct cells); the
+  // block's theta joins sigma * scale in the merge
   auto cval = [&](int rel, float sx, float sy) {
     return make_float2(__builtin_fmaf(th, sx, readlane_f(pre.x, rel)), __builtin_fmaf(th, sy, readlane_f(pre.y, rel)));
   };
@@ -1182,7 +1184,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     }
   };
   auto scatter_to = [&](const R(&g)[NK], float2(&A)[NK], const uint32_t(&adr)[NK], float2 c) {
-    const float vx = th * c.x, vy = th * c.y;
+    const float vx = c.x, vy = c.y;
 #pragma unroll
     for (int k = 0; k < NK; ++k) {
       const float gx = g_re<GP>(g[k]), gy = g_im<GP>(g[k]);
@@ -1197,7 +1199,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
     const int by = mt & 8191, bx = (mt >> 13) & 8191, S = 2 * (int)(mt >> 26) + 1;
     if (S != lay.S) lay.set(S, P, lane);
     const uint32_t base_b = ab + (uint32_t)((by - item.ty0) * P + (bx - item.tx0)) * 8u;
-    const float vx = th * c.x, vy = th * c.y;
+    const float vx = c.x, vy = c.y;
     float2 cur[NK];
 #pragma unroll
     for (int k = 0; k < NK; ++k) cur[k] = lds_load(lay.addr(base_b, k, apark));
@@ -1757,7 +1759,8 @@ __global__ __launch_bounds__(64 * kGatherWaves) void k_gather_kb(GArgs a, float2
   }
 }
 
-// Adds g theta c of a chunk's n visibilities, in order, into a wave's LDS
+// Adds conj(g) a of a chunk's n visibilities (a = theta v for the scatter, c
+// for the one pass), in order, into a wave's LDS
 // accumulator (byte base accb): for each visibility the lanes span its J x J
 // window (tap t = q 64 + lane at byte offset off[q] from the window origin,
 // weights from the table psi; lanes past the window use their spare cell)
@@ -1861,10 +1864,10 @@ __global__ __launch_bounds__(64) void k_scatter_kb(GArgs a, float2* __restrict__
 // accumulator in LDS.  Per 64-visibility chunk each lane evaluates its
 // visibility's 2J taps once, forms c = v / sigma + theta Phi x - y from the
 // tile (k_gather_kb's sum), writes c and its FP64 norm terms; then the taps
-// go to an LDS table and the wave adds g theta c of each visibility, in
+// go to an LDS table and the wave adds conj(g) c of each visibility, in
 // order, into the accumulator (k_scatter_kb's read-add-write of distinct
-// cells).  The partial holds G^H theta c; sigma_b * scale_b comes in v+
-// (k_vscale) and in the merge, as for stored G.
+// cells).  The partial holds G^H c; sigma_b * scale_b comes in v+ (k_vscale)
+// and, times theta_b, in the merge, as for stored G.
 template <int J>
 __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vis, const float2* __restrict__ yv,
                                                 double* __restrict__ item_norms, int it0, int it1) {
@@ -1940,7 +1943,7 @@ __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vi
         rho2 += (double)cc.x * (double)cc.x + (double)cc.y * (double)cc.y;
         res2 += rx * rx + ry * ry;
       }
-      const float avx = th * cc.x, avy = th * cc.y;
+      const float avx = cc.x, avy = cc.y;  // theta joins sigma * scale in the merge
       __syncthreads();  // the previous chunk's table reads are done
 #pragma unroll
       for (int i = 0; i < J; ++i) {
@@ -1973,17 +1976,20 @@ __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vi
 // reads of a partial row are coalesced.
 constexpr int kMergeList = 256;
 constexpr int kMergeSrc = 25;  // (rk + halo)^2 source tiles at most
-// Factor of an item's partial in the merge: sigma_b * scale_b after the fused
-// dual step (its partials hold G^H theta c), else 1 (exact: fma(1, v, s) = s + v).
-__device__ __forceinline__ float merge_factor(const double* sigma, const double* scale, int blk) {
-  return scale ? (float)((sigma ? sigma[blk] : 1.0) * scale[blk]) : 1.f;
+// Factor of an item's partial in the merge: sigma_b * scale_b * theta_b after
+// the one-pass dual step (its partials hold G^H c), else 1 (exact:
+// fma(1, v, s) = s + v).
+__device__ __forceinline__ float merge_factor(const double* sigma, const double* scale, const float* theta,
+                                              int blk) {
+  return scale ? (float)((sigma ? sigma[blk] : 1.0) * scale[blk] * (double)theta[blk]) : 1.f;
 }
 
 __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const float2* __restrict__ partials,
                                                const int32_t* __restrict__ tile_ptr,
                                                const TileEntry* __restrict__ ent, const int32_t* __restrict__ live,
                                                int live0, int Ky, int Kx, int T, int halo, int rk, int l0,
-                                               const double* __restrict__ sigma, const double* __restrict__ scale) {
+                                               const double* __restrict__ sigma, const double* __restrict__ scale,
+                                               const float* __restrict__ theta) {
   __shared__ int64_t s_off[kMergeList];
   __shared__ int32_t s_pitch[kMergeList];
   __shared__ float s_fac[kMergeList];
@@ -2025,7 +2031,7 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
     const TileEntry te = ent[s_beg[j] + (e - s_pre[j])];
     s_off[e] = te.poff;
     s_pitch[e] = te.pitch;
-    s_fac[e] = merge_factor(sigma, scale, te.blk);
+    s_fac[e] = merge_factor(sigma, scale, theta, te.blk);
     s_oy[e] = (halo - j / sw) * T;  // partial row of region row r: r + s_oy
     s_ox[e] = (halo - j % sw) * T;
   }
@@ -2040,7 +2046,7 @@ __global__ __launch_bounds__(256) void k_merge(float2* __restrict__ grid, const 
         const TileEntry te = ent[k];
         if ((unsigned)ly < (unsigned)te.pitch && (unsigned)lx < (unsigned)te.pitch) {
           const float2 v = partials[te.poff + (int64_t)ly * te.pitch + lx];
-          const float f = merge_factor(sigma, scale, te.blk);
+          const float f = merge_factor(sigma, scale, theta, te.blk);
           sx = __builtin_fmaf(f, v.x, sx);
           sy = __builtin_fmaf(f, v.y, sy);
         }
@@ -3017,14 +3023,15 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr, const TileEntry* entries,
                         const int32_t* live, int live0, int n_live, int Ky, int Kx, int T, int halo, int rk, int l0,
-                        int nl, const double* sigma, const double* scale, hipStream_t s) {
+                        int nl, const double* sigma, const double* scale, const float* theta, hipStream_t s) {
+  if (scale && !theta) return hipErrorInvalidValue;
   if (rk < 1 || rk > 2 || (rk + halo) * (rk + halo) > kMergeSrc || Ky % (rk * T) || Kx % (rk * T))
     return hipErrorInvalidValue;
   const int regions = (Ky / (rk * T)) * (Kx / (rk * T));
   if (live && n_live <= 0) return hipSuccess;
   const dim3 g = live ? dim3(n_live) : dim3(regions, nl);
   hipLaunchKernelGGL(k_merge, g, dim3(256), 0, s, grid, partials, tile_ptr, entries, live, live0, Ky, Kx, T, halo,
-                     rk, l0, sigma, scale);
+                     rk, l0, sigma, scale, theta);
   return hipGetLastError();
 }
 
