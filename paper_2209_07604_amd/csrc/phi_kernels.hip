@@ -934,9 +934,14 @@ __device__ __forceinline__ float2 lane_sum1(float a0, float a1) {
   const float q = row_sum16(fold16(h, h));  // rows: a0, a0, a1, a1
   return make_float2(readlane_f(q, 0), readlane_f(q, 32));
 }
+// Two windows p and q as one vector: its 16-lane rows hold sum p0, sum q0,
+// sum p1, sum q1 (every lane of a row the row's sum).
+__device__ __forceinline__ float lane_sum2v(float p0, float p1, float q0, float q1) {
+  return row_sum16(fold16(fold32(p0, p1), fold32(q0, q1)));
+}
 // Two windows p and q: (sum p0, sum p1, sum q0, sum q1).
 __device__ __forceinline__ float4 lane_sum2(float p0, float p1, float q0, float q1) {
-  const float q = row_sum16(fold16(fold32(p0, p1), fold32(q0, q1)));  // rows: p0, q0, p1, q1
+  const float q = lane_sum2v(p0, p1, q0, q1);
   return make_float4(readlane_f(q, 0), readlane_f(q, 32), readlane_f(q, 16), readlane_f(q, 48));
 }
 
@@ -1170,6 +1175,19 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
   auto cval = [&](int rel, float sx, float sy) {
     return make_float2(__builtin_fmaf(th, sx, readlane_f(pre.x, rel)), __builtin_fmaf(th, sy, readlane_f(pre.y, rel)));
   };
+  // Windows in pairs (rel, rel + 1): both c in one lane-parallel step on the
+  // pair's sum vector (rows: x of the first, x of the second, y of the
+  // first, y of the second), each lane taking the pre of its row's window
+  // and component from that window's lane (ds_bpermute); the same operation
+  // as cval, lane by lane.
+  const int pair_lane_b = ((lane >> 4) & 1) * 4;  // byte offset of the row's window from rel
+  const bool pair_y = lane >= 32;
+  auto pre_pair = [&](int rel) {
+    const int src = rel * 4 + pair_lane_b;
+    const float px = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(pre.x)));
+    const float py = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(pre.y)));
+    return pair_y ? py : px;
+  };
   const uint32_t apark = ab + (uint32_t)(P * P + lane) * 8u;  // this lane's spare cell
   // accumulator cells of a window, read ahead of its c (addresses kept for
   // the write-back; the layout may change before then)
@@ -1246,6 +1264,7 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
         // the two may share cells.
         float2 X0[NK], X1[NK], A0[NK];
         uint32_t adr0[NK];
+        const float pv = pre_pair(rel0 + d);
         cells(ms[d], X0);
         acc_cells(ms[d], A0, adr0);
         cells(ms[d + 1], X1);
@@ -1253,12 +1272,13 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
         settle(ax0, ay0);
         dot(gb[d + 1], X1, ax1, ay1);
         settle(ax1, ay1);
-        const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
-        place(rel0 + d, s.x, s.y);
-        scatter_to(gb[d], A0, adr0, cval(rel0 + d, s.x, s.y));
+        const float qv = lane_sum2v(ax0, ay0, ax1, ay1);
+        const float cv = __builtin_fmaf(th, qv, pv);
+        place(rel0 + d, readlane_f(qv, 0), readlane_f(qv, 32));
+        scatter_to(gb[d], A0, adr0, make_float2(readlane_f(cv, 0), readlane_f(cv, 32)));
         gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
-        place(rel0 + d + 1, s.z, s.w);
-        scatter(gb[d + 1], ms[d + 1], cval(rel0 + d + 1, s.z, s.w));
+        place(rel0 + d + 1, readlane_f(qv, 16), readlane_f(qv, 48));
+        scatter(gb[d + 1], ms[d + 1], make_float2(readlane_f(cv, 16), readlane_f(cv, 48)));
         gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
         continue;
       } else if constexpr (NK <= 3) {  // both windows' cell reads in flight together
@@ -1277,16 +1297,19 @@ __device__ __forceinline__ int64_t gather_item(const GArgs& a, const Item& item,
       }
       settle(ax1, ay1);
       if (MODE != 2) gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
-      const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
-      place(rel0 + d, s.x, s.y);
-      if (MODE == 2) {
-        scatter(gb[d], ms[d], cval(rel0 + d, s.x, s.y));
+      if constexpr (MODE == 2) {
+        const float qv = lane_sum2v(ax0, ay0, ax1, ay1);
+        const float cv = __builtin_fmaf(th, qv, pre_pair(rel0 + d));
+        place(rel0 + d, readlane_f(qv, 0), readlane_f(qv, 32));
+        scatter(gb[d], ms[d], make_float2(readlane_f(cv, 0), readlane_f(cv, 32)));
         gs.fetch(gb[d], ms[d], mcur, mnxt, cb, lane);
-      }
-      place(rel0 + d + 1, s.z, s.w);
-      if (MODE == 2) {
-        scatter(gb[d + 1], ms[d + 1], cval(rel0 + d + 1, s.z, s.w));
+        place(rel0 + d + 1, readlane_f(qv, 16), readlane_f(qv, 48));
+        scatter(gb[d + 1], ms[d + 1], make_float2(readlane_f(cv, 16), readlane_f(cv, 48)));
         gs.fetch(gb[d + 1], ms[d + 1], mcur, mnxt, cb, lane);
+      } else {
+        const float4 s = lane_sum2(ax0, ay0, ax1, ay1);
+        place(rel0 + d, s.x, s.y);
+        place(rel0 + d + 1, s.z, s.w);
       }
     }
     if constexpr (D & 1) single(D - 1, rel0 + D - 1, true);
