@@ -315,6 +315,14 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
       }
     w.chan_live0[l + 1] = (int32_t)w.live.size();
   }
+  // the same regions as bits, one row of words per region row of a channel
+  w.live_wpr = (nrx + 31) / 32;
+  w.live_bits.assign((size_t)p->L * nry * w.live_wpr, 0u);
+  for (int32_t t : w.live) {
+    const int64_t row = t / nrx;
+    const int rx = (int)(t % nrx);
+    w.live_bits[(size_t)row * w.live_wpr + rx / 32] |= 1u << (rx % 32);
+  }
 }
 
 bool phi_plan_s::fused() const {
@@ -337,14 +345,16 @@ static void layout(phi_plan_s* p, size_t base = 0, const phi_plan_s* share = nul
   p->off_frac = take(p->gprec == PHI_G_KB ? (size_t)p->M * 8 : 0);  // (kappa - b) per visibility, FP32
   p->off_meta = take((size_t)p->M * 4);
   p->off_perm = take((size_t)p->M * 4);
-  size_t n_items = 0, n_tptr = 0, n_part = 0, n_live = 0;
+  size_t n_items = 0, n_tptr = 0, n_part = 0, n_live = 0, n_bits = 0;
   for (const WorkList& w : p->cands) {
     n_items = std::max(n_items, w.items.size());
     n_tptr = std::max(n_tptr, w.tile_ptr.size());
     n_part = std::max(n_part, (size_t)w.partial_elems);
     n_live = std::max(n_live, w.live.size());
+    n_bits = std::max(n_bits, w.live_bits.size());
   }
   p->off_live = take(n_live * 4);
+  p->off_live_bits = take(n_bits * 4);
   p->off_items = take(n_items * sizeof(Item));
   p->off_items_p = take(n_items * sizeof(Item));
   p->off_binfo = take((size_t)p->nblk * sizeof(BlockInfo));
@@ -395,6 +405,7 @@ static hipError_t upload_worklist(phi_plan_s* p, hipStream_t s) {
   up(p->off_tptr, w.tile_ptr.data(), w.tile_ptr.size() * 4);
   up(p->off_ent, w.entries.data(), w.entries.size() * sizeof(TileEntry));
   up(p->off_live, w.live.data(), w.live.size() * 4);
+  up(p->off_live_bits, w.live_bits.data(), w.live_bits.size() * 4);
   // the adjoint grid starts at zero: the merge of this tiling writes only
   // its live tiles, and no window reaches the others' cells
   if (e == hipSuccess && p->sparse_merge)
@@ -913,6 +924,12 @@ struct Runner {
       p->timer.pending.push_back({id, {e0, e1}});
     }
   }
+  // The merge regions some partial reaches, as bits, where the sparse merge
+  // runs (the adjoint grid is zero elsewhere); else none (every cell).
+  LiveRegions live_regions() const {
+    const WorkList& w = p->W();
+    return LiveRegions{p->sparse_merge ? p->at<uint32_t>(p->off_live_bits) : nullptr, w.merge_rk * w.T, w.live_wpr};
+  }
   // channel range [l0, l1), matching block and item ranges
   void fwd_fft(const float* x, int l0, int l1) {
     const int nl = l1 - l0;
@@ -956,9 +973,11 @@ struct Runner {
     if (fft_image_first(p->Ky, p->Nx)) {
       // rows first (the Nx kept columns into the half grid), then the image's
       // columns (packed columns in the grid buffer), real part, Z^T
+      // with the sparse merge, the row pass reads only the live regions'
+      // cells (the others are zero)
       stage(7, [&] {
         return launch_rowc_inv(p->Kx, p->at<float2>(p->off_grid_a), p->at<float2>(p->off_half),
-                               p->at<float2>(p->off_twx), p->Ky, l0, nl, s);
+                               p->at<float2>(p->off_twx), p->Ky, l0, nl, live_regions(), s);
       });
       stage(6, [&] {
         return launch_colr_inv(p->Ky, p->at<float2>(p->off_half), p->at<float2>(p->off_grid), x,

@@ -88,12 +88,22 @@ hipError_t launch_rowfft_inv(int Kx, const float2* half, float* x, const float* 
 // scratch [L][Ky][Nx/2], T: [L][Ky][Nx]), then the Ky rows of T into the
 // grid; the adjoint runs the mirror.
 bool fft_image_first(int Ky, int Nx);
-hipError_t launch_colr_fwd(int Ky, const float* x, float2* zp, float2* T, const float* sy, const float* sx,
-                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
 hipError_t launch_rowc_fwd(int Kx, const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl,
                            hipStream_t s);
+hipError_t launch_colr_fwd(int Ky, const float* x, float2* zp, float2* T, const float* sy, const float* sx,
+                           const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
+
+// Regions of R x R grid cells known to be zero outside the live ones: bit
+// rx % 32 of word (l * (Ky / R) + ry) * wpr + rx / 32 marks region (ry, rx)
+// of channel l live; bits null: every cell is read.
+struct LiveRegions {
+  const uint32_t* bits;
+  int R, wpr;
+};
+// The inverse row pass reads only the live regions' cells when live.bits is
+// set (the others are zero).
 hipError_t launch_rowc_inv(int Kx, const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl,
-                           hipStream_t s);
+                           LiveRegions live, hipStream_t s);
 hipError_t launch_colr_inv(int Ky, const float2* T, float2* zp, float* x, const float* sy, const float* sx,
                            const float2* tw, int Ny, int Nx, int l0, int nl, hipStream_t s);
 

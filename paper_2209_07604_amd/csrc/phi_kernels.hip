@@ -722,7 +722,7 @@ template <int N, int NT>
 __global__ __launch_bounds__(NT, (rowc_inv_waves<N, NT>())) void k_rowc_inv_p(const float2* __restrict__ grid,
                                                                    float2* __restrict__ T,
                                                                    const float2* __restrict__ tw, int Ky, int l0,
-                                                                   int nrows) {
+                                                                   int nrows, LiveRegions live) {
   constexpr int M = N / 2, Nx = M, PT = (M + NT - 1) / NT, NW = tw_table_size(M);
   __shared__ float2 buf[N + N / 16];  // padded
   __shared__ float2 tab[NW > 0 ? NW : 1];
@@ -731,13 +731,30 @@ __global__ __launch_bounds__(NT, (rowc_inv_waves<N, NT>())) void k_rowc_inv_p(co
   tw_table<M, NT, 1, 2>(tab, tw);
   if (tid < 64) s_lane[tid] = tid < N ? tw[tid] : make_float2(1.f, 0.f);
   float4 v[PT];
+  // With live regions, a wave's 64 element pairs (128 cells) lie in
+  // 128 / R <= 8 regions of one mask word (R >= 16, a power of two): where
+  // none of them is live the wave loads nothing (its cells are zero); the
+  // test is wave-uniform.
+  const int wave_pair0 = __builtin_amdgcn_readfirstlane(tid & ~63);  // the wave's first pair (at q = 0)
   auto load = [&](int r) {
     const int l = l0 + r / Ky, k = r % Ky;
     const float4* in = reinterpret_cast<const float4*>(grid + ((size_t)l * Ky + k) * N);
+    const uint32_t* mrow = live.bits ? live.bits + ((size_t)l * (Ky / live.R) + k / live.R) * live.wpr : nullptr;
+    uint32_t word[PT];  // the mask words, all loaded before the first test
+#pragma unroll
+    for (int q = 0; q < PT; ++q) word[q] = mrow ? mrow[(2 * (wave_pair0 + q * NT) / live.R) >> 5] : ~0u;
 #pragma unroll
     for (int q = 0; q < PT; ++q) {
       const int i = tid + q * NT;
-      if (M % NT == 0 || i < M) v[q] = in[i];
+      if (M % NT == 0 || i < M) {
+        const int reg0 = 2 * (wave_pair0 + q * NT) / live.R, nreg = 128 / live.R;
+        const bool dead = mrow && ((word[q] >> (reg0 & 31)) & ((1u << nreg) - 1u)) == 0u;
+        if (dead) {
+          v[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+          v[q] = in[i];
+        }
+      }
     }
   };
   int r = blockIdx.x;
@@ -2797,6 +2814,12 @@ int resident_groups(K kernel, int threads, int* cache) {
   }
   return cache[dev];
 }
+// Region masks of the inverse row pass: R a power of two >= 16 dividing Ky
+// and N, one word per 32 regions of a row.
+bool live_regions_fit(const LiveRegions& live, int N, int Ky) {
+  return !live.bits || (live.R >= 16 && !(live.R & (live.R - 1)) && Ky % live.R == 0 && N % live.R == 0 &&
+                        live.wpr * 32 >= N / live.R);
+}
 template <int N, int NT>
 hipError_t rowc_fwd_nt(const float2* T, float2* grid, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
   static int cache[64] = {0};
@@ -2807,12 +2830,15 @@ hipError_t rowc_fwd_nt(const float2* T, float2* grid, const float2* tw, int Ky, 
   return hipGetLastError();
 }
 template <int N, int NT>
-hipError_t rowc_inv_nt(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+hipError_t rowc_inv_nt(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, LiveRegions live,
+                       hipStream_t s) {
   static int cache[64] = {0};
+  if (!live_regions_fit(live, N, Ky)) return hipErrorInvalidValue;
   const int g = resident_groups(k_rowc_inv_p<N, NT>, NT, cache);
   if (g <= 0) return hipErrorInvalidDevice;
   const int nrows = Ky * nl;
-  hipLaunchKernelGGL((k_rowc_inv_p<N, NT>), dim3(std::min(g, nrows)), dim3(NT), 0, s, grid, T, tw, Ky, l0, nrows);
+  hipLaunchKernelGGL((k_rowc_inv_p<N, NT>), dim3(std::min(g, nrows)), dim3(NT), 0, s, grid, T, tw, Ky, l0, nrows,
+                     live);
   return hipGetLastError();
 }
 template <int N>
@@ -2824,9 +2850,10 @@ hipError_t rowc_fwd_n(const float2* T, float2* grid, const float2* tw, int Ky, i
 // points: 2.83 ms against 3.11 ms with 1024 threads, which spill the prefetch;
 // the forward is faster with 1024, 2.76 against 2.85 ms).
 template <int N>
-hipError_t rowc_inv_n(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, hipStream_t s) {
+hipError_t rowc_inv_n(const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl, LiveRegions live,
+                      hipStream_t s) {
   constexpr int NT = N >= 2048 ? rowc_threads<N>() / 2 : rowc_threads<N>();
-  return rowc_inv_nt<N, NT>(grid, T, tw, Ky, l0, nl, s);
+  return rowc_inv_nt<N, NT>(grid, T, tw, Ky, l0, nl, live, s);
 }
 
 #define PHI_FFT_SIZES(X)                                                                              \
@@ -3200,11 +3227,11 @@ hipError_t launch_rowc_fwd(int Kx, const float2* T, float2* grid, const float2* 
   }
 }
 hipError_t launch_rowc_inv(int Kx, const float2* grid, float2* T, const float2* tw, int Ky, int l0, int nl,
-                           hipStream_t s) {
+                           LiveRegions live, hipStream_t s) {
   switch (Kx) {
 #define X(N) \
   case N:    \
-    return rowc_inv_n<N>(grid, T, tw, Ky, l0, nl, s);
+    return rowc_inv_n<N>(grid, T, tw, Ky, l0, nl, live, s);
     PHI_FFT_SIZES(X)
 #undef X
     default:

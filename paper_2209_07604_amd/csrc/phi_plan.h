@@ -47,6 +47,10 @@ struct WorkList {
   int merge_rk = 1;
   std::vector<int32_t> live;
   std::vector<int32_t> chan_live0;          // [L + 1]
+  // the live regions as bits: word (l * (Ky / R) + ry) * live_wpr + rx / 32,
+  // bit rx % 32 (R = merge_rk * T)
+  int live_wpr = 1;
+  std::vector<uint32_t> live_bits;
   // the items again, by pitch (largest first), for launches whose LDS is
   // sized per pitch; runs of equal pitch as (pitch, first, end)
   std::vector<Item> items_by_pitch;
@@ -87,8 +91,8 @@ struct phi_plan_s {
   WorkList& W() { return cands[cur]; }
   const WorkList& W() const { return cands[cur]; }
   // workspace layout
-  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_items_p = 0, off_binfo = 0,
-         off_tptr = 0, off_ent = 0,
+  size_t off_bpart = 0, off_G = 0, off_meta = 0, off_perm = 0, off_items = 0, off_items_p = 0, off_live_bits = 0,
+         off_binfo = 0, off_tptr = 0, off_ent = 0,
          off_theta = 0, off_part = 0, off_norms = 0, off_scale = 0, off_flag = 0, off_grid = 0, off_half = 0,
          off_twx = 0, off_twy = 0, off_sy = 0, off_sx = 0, off_vscr = 0, off_anal = 0, off_frac = 0, ws_bytes = 0,
          off_grid_a = 0, off_live = 0;
