@@ -563,18 +563,29 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_a(const float* __restrict__ x, 
     const int e = threadIdx.x + i * NT;
     wst[i] = tw[e < N2 * W ? n1 * (e / W) : 0];
   }
+  // a thread's elements share one column pair (NT is a multiple of W); all
+  // its loads go out before the first is used
+  static_assert(NT % W == 0, "one column pair per thread");
   const float* xi = x + (size_t)l * Ny * Nx;
-  for (int e = threadIdx.x; e < N2 * W; e += NT) {
-    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+  const int q = 2 * (c0 + (int)threadIdx.x % W);
+  const float sxa = sx[q], sxb = sx[q + 1];
+  float2 xv[PER];
+  float sv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, n = n1 + N1 * (e / W);
     const int p = (n < N / 2 ? n : n - N) + Ny / 2;
-    float2 v = make_float2(0.f, 0.f);
-    if (p >= 0 && p < Ny) {
-      const int q = 2 * (c0 + c);
-      const float2 xv = *reinterpret_cast<const float2*>(xi + (size_t)p * Nx + q);
-      const float s = sy[p];
-      v = make_float2(s * sx[q] * xv.x, s * sx[q + 1] * xv.y);
+    xv[i] = make_float2(0.f, 0.f);
+    sv[i] = 0.f;
+    if (e < N2 * W && p >= 0 && p < Ny) {
+      xv[i] = *reinterpret_cast<const float2*>(xi + (size_t)p * Nx + q);
+      sv[i] = sy[p];
     }
-    buf[e] = v;
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N2 * W) buf[e] = make_float2(sv[i] * sxa * xv[i].x, sv[i] * sxb * xv[i].y);
   }
   __syncthreads();
   fft_run<N2, W, NT, false, false>(buf, tab, threadIdx.x);
@@ -867,28 +878,46 @@ __global__ __launch_bounds__(NT) void k_colr_inv_a(const float2* __restrict__ zp
                                                    const float* __restrict__ sy, const float* __restrict__ sx,
                                                    const float2* __restrict__ tw, int Ny, int Nx, int l0,
                                                    size_t zs) {
-  constexpr int N = N1 * N2;
+  constexpr int N = N1 * N2, PER = (N2 * W + NT - 1) / NT;
+  static_assert(NT % W == 0, "one column pair per thread");
   __shared__ float2 buf[N2 * W];
   __shared__ float2 tab[tw_tab_len<N2>()];
   tw_table<N2, NT, 1, N1>(tab, tw);
   const int Nh = Nx / 2, npc = Nh / W;
   const int n1 = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
   const float2* in = zp + (size_t)l * zs + (size_t)N2 * n1 * Nh;
-  for (int e = threadIdx.x; e < N2 * W; e += NT) {
-    const int k2 = e / W, c = e % W;
-    buf[e] = in[(size_t)k2 * Nh + c0 + c];
+  // all of a thread's loads go out before the first is used (here and for
+  // the scales below)
+  float2 zv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N2 * W) zv[i] = in[(size_t)(e / W) * Nh + c0 + e % W];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N2 * W) buf[e] = zv[i];
+  }
+  const int q = 2 * (c0 + (int)threadIdx.x % W);
+  const float sxa = sx[q], sxb = sx[q + 1];
+  float sv[PER];
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, n = n1 + N1 * (e / W);
+    const int p = (n < N / 2 ? n : n - N) + Ny / 2;
+    sv[i] = e < N2 * W && p >= 0 && p < Ny ? sy[p] : 0.f;
   }
   __syncthreads();
   fft_run<N2, W, NT, true, false>(buf, tab, threadIdx.x);
   float* xo = x + (size_t)l * Ny * Nx;
-  for (int e = threadIdx.x; e < N2 * W; e += NT) {
-    const int n2 = e / W, c = e % W, n = n1 + N1 * n2;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, n = n1 + N1 * (e / W);
     const int p = (n < N / 2 ? n : n - N) + Ny / 2;
-    if (p >= 0 && p < Ny) {
-      const int q = 2 * (c0 + c);
-      const float s = sy[p];
+    if (e < N2 * W && p >= 0 && p < Ny) {
       const float2 v = buf[e];
-      *reinterpret_cast<float2*>(xo + (size_t)p * Nx + q) = make_float2(s * sx[q] * v.x, s * sx[q + 1] * v.y);
+      *reinterpret_cast<float2*>(xo + (size_t)p * Nx + q) = make_float2(sv[i] * sxa * v.x, sv[i] * sxb * v.y);
     }
   }
 }
