@@ -385,10 +385,19 @@ __global__ __launch_bounds__(NT) void k_colfft_fwd(const float2* __restrict__ ha
   const int np = Kx / W;
   const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
   const float2* in = half + (size_t)l * Ny * Kx;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int k = e / W, c = e % W;
+  constexpr int PER = (N * W + NT - 1) / NT;
+  float2 v[PER];  // all of a thread's loads go out before the first is used
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT, k = e / W, c = e % W;
     const int p = (k < N / 2 ? k : k - N) + Ny / 2;
-    buf[e] = (p >= 0 && p < Ny) ? in[(size_t)p * Kx + c0 + c] : make_float2(0.f, 0.f);
+    v[i] = make_float2(0.f, 0.f);
+    if (e < N * W && p >= 0 && p < Ny) v[i] = in[(size_t)p * Kx + c0 + c];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N * W) buf[e] = v[i];
   }
   __syncthreads();
   fft_run<N, W, NT, false, false>(buf, tab, threadIdx.x);
@@ -410,9 +419,17 @@ __global__ __launch_bounds__(NT) void k_colfft_inv(const float2* __restrict__ gr
   const int np = Kx / W;
   const int c0 = xcd_remap(blockIdx.x, np) * W, l = l0 + blockIdx.y;
   const float2* in = grid + (size_t)l * N * Kx;
-  for (int e = threadIdx.x; e < N * W; e += NT) {
-    const int k = e / W, c = e % W;
-    buf[e] = in[(size_t)k * Kx + c0 + c];
+  constexpr int PER = (N * W + NT - 1) / NT;
+  float2 v[PER];  // all of a thread's loads go out before the first is used
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N * W) v[i] = in[(size_t)(e / W) * Kx + c0 + e % W];
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N * W) buf[e] = v[i];
   }
   __syncthreads();
   fft_run<N, W, NT, true, false>(buf, tab, threadIdx.x);
@@ -622,9 +639,20 @@ __global__ __launch_bounds__(NT) void k_colr_fwd_b(const float2* __restrict__ zp
   const int g = blockIdx.x / npc, c0 = xcd_remap(blockIdx.x % npc, npc) * W, l = l0 + blockIdx.y;
   const int k2a = g, k2b = (N2 - g) % N2;
   const float2* in = zp + (size_t)l * zs;
-  for (int e = threadIdx.x; e < N1 * W2; e += NT) {
-    const int j = e / W2, col = e % W2, c = col % W, k2 = col < W ? k2a : k2b;
-    buf[e] = in[(size_t)(N2 * j + k2) * Nh + c0 + c];
+  constexpr int PER = (N1 * W2 + NT - 1) / NT;
+  float2 zv[PER];  // all of a thread's loads go out before the first is used
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W2) {
+      const int j = e / W2, col = e % W2, c = col % W, k2 = col < W ? k2a : k2b;
+      zv[i] = in[(size_t)(N2 * j + k2) * Nh + c0 + c];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int e = threadIdx.x + i * NT;
+    if (e < N1 * W2) buf[e] = zv[i];
   }
   __syncthreads();
   fft_run<N1, W2, NT, false, false>(buf, tab, threadIdx.x);
