@@ -291,12 +291,19 @@ static void build_worklist(const phi_plan_s* p, int T, WorkList& w) {
   }
   w.halo = (p->smax - 1 + T - 1) / T;
   if (w.halo < 1) w.halo = 1;
-  // merge regions of rk x rk tiles, 32 cells wide where the tile grid allows
-  // (16-cell tiles on the 16 x 4096^2 workload: 4.51 -> 3.53 ms; 64-cell
-  // regions: 6.27 ms); live regions: those whose merge list (the partials of
-  // their own tiles and of the tiles up to `halo` above / left, with wrap) is
-  // not empty
-  const int rk = (T == 16 && nty % 2 == 0 && ntx % 2 == 0 && (2 + w.halo) * (2 + w.halo) <= 25) ? 2 : 1;
+  // merge regions of rk x rk tiles at 16-cell tiles, where the tile grid
+  // allows: 64 cells wide where that still gives 64K regions or more (each
+  // work-group takes four times the cells, so fewer regions leave a longer
+  // tail: 16 x 4096^2 workload, 262K regions: 2.39 -> 2.28 ms against
+  // 32-cell regions; 16 x 1024^2 workload, 16K: 0.28 -> 0.33 ms), else 32
+  // (4.51 -> 3.53 ms against one tile); live regions: those whose merge list
+  // (the partials of their own tiles and of the tiles up to `halo` above /
+  // left, with wrap) is not empty
+  const bool many64 = (int64_t)p->L * (nty / 4) * (ntx / 4) >= 65536;
+  const int rk =
+      (T == 16 && many64 && nty % 4 == 0 && ntx % 4 == 0 && (4 + w.halo) * (4 + w.halo) <= 25) ? 4
+      : (T == 16 && nty % 2 == 0 && ntx % 2 == 0 && (2 + w.halo) * (2 + w.halo) <= 25)         ? 2
+                                                                                               : 1;
   w.merge_rk = rk;
   const int nry = nty / rk, nrx = ntx / rk;
   w.live.clear();

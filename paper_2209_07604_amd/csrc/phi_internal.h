@@ -127,7 +127,7 @@ hipError_t launch_scatter(int gprec, int mode, const GArgs& a, float2* vis, floa
 // sigma/scale/theta: per-block factors sigma_b * scale_b * theta_b applied to
 // each item's partial (entry .blk) after the one-pass dual step (sigma null:
 // 1), or scale null for factor 1.  A work-group merges a region of rk x rk
-// tiles (rk 1 or 2).  live: the regions to write, live[live0 .. live0 +
+// tiles (rk 1, 2 or 4).  live: the regions to write, live[live0 .. live0 +
 // n_live) (channel-major region indices), or null for every region of
 // channels [l0, l0 + nl).
 hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* tile_ptr,

@@ -2064,7 +2064,7 @@ __global__ __launch_bounds__(64) void k_dual_kb(GArgs a, float2* __restrict__ vi
 }
 
 // One work-group per (channel, region): a region is rk x rk tiles of edge T
-// (rk = 1 or 2), and cell (r, c) of it is the fixed-order sum of the tile
+// (rk = 1, 2 or 4), and cell (r, c) of it is the fixed-order sum of the tile
 // partials covering it: those of the tiles up to `halo` tiles above / left
 // of the region and of its own tiles (with wrap), source tile by source
 // tile, items in tile order.  A 2 x 2 region reads each of its own tiles'
@@ -3132,7 +3132,7 @@ hipError_t launch_merge(float2* grid, const float2* partials, const int32_t* til
                         const int32_t* live, int live0, int n_live, int Ky, int Kx, int T, int halo, int rk, int l0,
                         int nl, const double* sigma, const double* scale, const float* theta, hipStream_t s) {
   if (scale && !theta) return hipErrorInvalidValue;
-  if (rk < 1 || rk > 2 || (rk + halo) * (rk + halo) > kMergeSrc || Ky % (rk * T) || Kx % (rk * T))
+  if (rk < 1 || rk > 4 || (rk + halo) * (rk + halo) > kMergeSrc || Ky % (rk * T) || Kx % (rk * T))
     return hipErrorInvalidValue;
   const int regions = (Ky / (rk * T)) * (Kx / (rk * T));
   if (live && n_live <= 0) return hipSuccess;
